@@ -1,0 +1,160 @@
+"""Model terms for the oracle (test infrastructure only; never imported by the
+product path).
+
+For a state-space model of the paper's form (Sec. 2.1, eq. statespace)
+
+    dx/dt = f(x) + L w,   y = h(x) + v,   w, v white with spectral densities W, R,
+
+the linear-affine model of Sec. 2.4 (eq. linear-statespace) used at one
+Gauss--Newton iteration is the first-order Taylor expansion about a nominal
+state xbar (Sec. 4.4):
+
+    F = df/dx(xbar),  c = f(xbar) - F xbar,  H = dh/dx(xbar),  r = h(xbar) - H xbar.
+
+Every term is evaluated at the right end of its grid step, i.e. at the state
+x_k the step leads to.  Two implementations are given: torch (differentiable
+in theta, for gradient truth by autograd) and numpy (vectorised over steps,
+feeding the C oracle).
+
+Parameter vectors:
+  cv        (gamma, q, r): F = [[0, I], [0, -gamma I]], c = 0, L = [0; I], W = q I,
+                           H = [I, 0], r = 0, R = r I          (nx = 2d, ny = nw = d)
+  vdp       (mu, q, r):    f = (x2, mu (1 - x1^2) x2 - x1), L = I, W = q I,
+                           h = x1, R = r                        (nx = 2, ny = 1, nw = 2)
+  lorenz63  (sigma, rho, beta, q, r): f = (sigma (x2 - x1), x1 (rho - x3) - x2,
+                           x1 x2 - beta x3), L = I, W = q I, h = x, R = r I  (nx = ny = nw = 3)
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def dims(model: str, nx: int):
+    if model == "cv":
+        return nx, nx // 2, nx // 2
+    if model == "vdp":
+        return 2, 1, 2
+    if model == "lorenz63":
+        return 3, 3, 3
+    raise ValueError(model)
+
+
+# ----------------------------------------------------------------------------- torch
+
+def terms_torch(model: str, theta: torch.Tensor, xbar: torch.Tensor, nx: int):
+    """theta [n_theta]; xbar [T, nx] (the right-end state of each step).
+    Returns F [T,nx,nx], c [T,nx], L [nx,nw], W [nw,nw], H [T,ny,nx], r [T,ny], R [ny,ny]."""
+    T = xbar.shape[0]
+    dt_ = theta.dtype
+    if model == "cv":
+        d = nx // 2
+        g, q, rr = theta[0], theta[1], theta[2]
+        I = torch.eye(d, dtype=dt_)
+        Z = torch.zeros(d, d, dtype=dt_)
+        F = torch.cat([torch.cat([Z, I], 1), torch.cat([Z, -g * I], 1)], 0)
+        F = F.expand(T, nx, nx)
+        c = torch.zeros(T, nx, dtype=dt_)
+        L = torch.cat([Z, I], 0)
+        W = q * I
+        H = torch.cat([I, Z], 1).expand(T, d, nx)
+        r = torch.zeros(T, d, dtype=dt_)
+        R = rr * I
+        return F, c, L, W, H, r, R
+    if model == "vdp":
+        mu, q, rr = theta[0], theta[1], theta[2]
+        x1, x2 = xbar[:, 0], xbar[:, 1]
+        zero = torch.zeros_like(x1)
+        one = torch.ones_like(x1)
+        F = torch.stack([torch.stack([zero, one], 1),
+                         torch.stack([-2.0 * mu * x1 * x2 - 1.0, mu * (1.0 - x1 * x1)], 1)], 1)
+        f = torch.stack([x2, mu * (1.0 - x1 * x1) * x2 - x1], 1)
+        c = f - torch.einsum("kij,kj->ki", F, xbar)
+        L = torch.eye(2, dtype=dt_)
+        W = q * torch.eye(2, dtype=dt_)
+        H = torch.tensor([[1.0, 0.0]], dtype=dt_).expand(T, 1, 2)
+        r = torch.zeros(T, 1, dtype=dt_)
+        R = rr.reshape(1, 1)
+        return F, c, L, W, H, r, R
+    if model == "lorenz63":
+        sg, rho, be, q, rr = theta[0], theta[1], theta[2], theta[3], theta[4]
+        x1, x2, x3 = xbar[:, 0], xbar[:, 1], xbar[:, 2]
+        one = torch.ones_like(x1)
+        F = torch.stack([torch.stack([-sg * one, sg * one, 0.0 * one], 1),
+                         torch.stack([rho - x3, -one, -x1], 1),
+                         torch.stack([x2, x1, -be * one], 1)], 1)
+        f = torch.stack([sg * (x2 - x1), x1 * (rho - x3) - x2, x1 * x2 - be * x3], 1)
+        c = f - torch.einsum("kij,kj->ki", F, xbar)
+        L = torch.eye(3, dtype=dt_)
+        W = q * torch.eye(3, dtype=dt_)
+        H = torch.eye(3, dtype=dt_).expand(T, 3, 3)
+        r = torch.zeros(T, 3, dtype=dt_)
+        R = rr * torch.eye(3, dtype=dt_)
+        return F, c, L, W, H, r, R
+    raise ValueError(model)
+
+
+def drift_torch(model: str, theta: torch.Tensor, x: torch.Tensor, nx: int):
+    """The nonlinear drift f(x) and measurement h(x), x [T, nx]."""
+    if model == "cv":
+        d = nx // 2
+        g = theta[0]
+        f = torch.cat([x[:, d:], -g * x[:, d:]], 1)
+        return f, x[:, :d]
+    if model == "vdp":
+        mu = theta[0]
+        x1, x2 = x[:, 0], x[:, 1]
+        return torch.stack([x2, mu * (1.0 - x1 * x1) * x2 - x1], 1), x[:, :1]
+    if model == "lorenz63":
+        sg, rho, be = theta[0], theta[1], theta[2]
+        x1, x2, x3 = x[:, 0], x[:, 1], x[:, 2]
+        return torch.stack([sg * (x2 - x1), x1 * (rho - x3) - x2, x1 * x2 - be * x3], 1), x
+    raise ValueError(model)
+
+
+# ----------------------------------------------------------------------------- numpy
+
+def terms_numpy(model: str, theta: np.ndarray, xbar: np.ndarray, nx: int):
+    """Same terms as `terms_torch`, vectorised: theta [n_theta] (one segment),
+    xbar [T, nx].  Per-step arrays have a leading T axis."""
+    T = xbar.shape[0]
+    if model == "cv":
+        d = nx // 2
+        g, q, rr = theta
+        F = np.zeros((nx, nx))
+        F[:d, d:] = np.eye(d)
+        F[d:, d:] = -g * np.eye(d)
+        L = np.zeros((nx, d))
+        L[d:, :] = np.eye(d)
+        H = np.zeros((d, nx))
+        H[:, :d] = np.eye(d)
+        return (np.broadcast_to(F, (T, nx, nx)), np.zeros((T, nx)), L, q * np.eye(d),
+                np.broadcast_to(H, (T, d, nx)), np.zeros((T, d)), rr * np.eye(d))
+    if model == "vdp":
+        mu, q, rr = theta
+        x1, x2 = xbar[:, 0], xbar[:, 1]
+        F = np.zeros((T, 2, 2))
+        F[:, 0, 1] = 1.0
+        F[:, 1, 0] = -2.0 * mu * x1 * x2 - 1.0
+        F[:, 1, 1] = mu * (1.0 - x1 * x1)
+        f = np.stack([x2, mu * (1.0 - x1 * x1) * x2 - x1], 1)
+        c = f - np.einsum("kij,kj->ki", F, xbar)
+        H = np.broadcast_to(np.array([[1.0, 0.0]]), (T, 1, 2))
+        return F, c, np.eye(2), q * np.eye(2), H, np.zeros((T, 1)), np.array([[rr]])
+    if model == "lorenz63":
+        sg, rho, be, q, rr = theta
+        x1, x2, x3 = xbar[:, 0], xbar[:, 1], xbar[:, 2]
+        F = np.zeros((T, 3, 3))
+        F[:, 0, 0] = -sg
+        F[:, 0, 1] = sg
+        F[:, 1, 0] = rho - x3
+        F[:, 1, 1] = -1.0
+        F[:, 1, 2] = -x1
+        F[:, 2, 0] = x2
+        F[:, 2, 1] = x1
+        F[:, 2, 2] = -be
+        f = np.stack([sg * (x2 - x1), x1 * (rho - x3) - x2, x1 * x2 - be * x3], 1)
+        c = f - np.einsum("kij,kj->ki", F, xbar)
+        H = np.broadcast_to(np.eye(3), (T, 3, 3))
+        return F, c, np.eye(3), q * np.eye(3), H, np.zeros((T, 3)), rr * np.eye(3)
+    raise ValueError(model)

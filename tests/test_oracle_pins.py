@@ -1,0 +1,241 @@
+"""Pins of the CPU oracle against things that do not come from the oracle.
+
+Each test names what fixes the expected value: dense Gaussian conditioning
+of the discrete model, dense least squares of the discretised
+Onsager--Machlup objective, the discrete algebraic Riccati equation, the
+closed-form continuous-time Riccati solution of the Wiener velocity model,
+central finite differences of a dense likelihood, and nonlinear least squares.
+Every linear case has c != 0 and r != 0 somewhere (an S_k / S_{k-1} slip in
+an information-vector update only shows when the element offset b is
+nonzero).
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+import torch
+
+import workloads
+from oracle import cref, ref
+from tests import _dense
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def _cases():
+    return [
+        workloads.linear_random(T=24, nx=3, ny=2, nw=3, seed=21),          # dense Q, c, r != 0
+        workloads.linear_random(T=20, nx=4, ny=2, nw=2, seed=22),          # singular Q
+        workloads.cv(T=18, d=2, dt=0.05, gamma=0.4, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                     P0=1e-2 * np.eye(4), seed=23),                         # CV, singular Q
+        workloads.linear_random(T=16, nx=2, ny=1, nw=2, seed=24, time_varying=False),
+    ]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_smoother_equals_dense_conditioning(case):
+    wl = _cases()[case]
+    o = cref.smooth(wl)
+    mean, cov, ll = _dense.dense_posterior(wl, 0)
+    T = wl.n_steps
+    nx = wl.nx
+    assert np.abs(o["xs"] - mean).max() <= 1e-11 * max(1.0, np.abs(mean).max())
+    dcov = np.stack([cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] for k in range(T + 1)])
+    assert np.abs(o["Ps"] - dcov).max() <= 1e-11 * max(1.0, np.abs(dcov).max())
+    assert abs(o["loglik"][0] - ll) <= 1e-10 * max(1.0, abs(ll))
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_filter_equals_dense_conditioning(case):
+    wl = _cases()[case]
+    o = cref.smooth(wl)
+    nx = wl.nx
+    for k in (1, wl.n_steps // 2, wl.n_steps):
+        mean, cov, _ = _dense.dense_posterior(wl, 0, upto=k)
+        assert np.abs(o["m"][k] - mean[k]).max() <= 1e-11 * max(1.0, np.abs(mean).max())
+        ck = cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx]
+        assert np.abs(o["P"][k] - ck).max() <= 1e-11 * max(1.0, np.abs(ck).max())
+
+
+@pytest.mark.parametrize("case", [0, 3])
+def test_map_estimate_equals_dense_least_squares(case):
+    """With invertible Q the smoother mean is the minimiser of the discretised
+    objective and M* its minimum value."""
+    wl = _cases()[case]
+    o = cref.smooth(wl)
+    x, val = _dense.dense_least_squares(wl, 0)
+    assert np.abs(o["xs"] - x).max() <= 1e-10 * max(1.0, np.abs(x).max())
+    assert abs(o["mstar"][0] - val) <= 1e-10 * max(1.0, abs(val))
+
+
+def test_mstar_singular_q_equals_conditioned_limit():
+    """For singular Q, M* is the limit of the invertible-Q minimum value as the
+    missing noise directions vanish: check continuity against a tiny added W
+    direction (dense least squares on a full-rank L)."""
+    wl = workloads.cv(T=16, d=1, dt=0.1, gamma=0.3, q=0.7, r=0.2, seed=31)
+    o = cref.smooth(wl)
+    vals = []
+    for eps in (1e-6, 1e-7):
+        wl2 = workloads.linear_random(T=16, nx=2, ny=1, nw=2, seed=1)
+        F, c, L, W, H, r, R = _dense.step_terms(wl, 0)
+        T = wl.n_steps
+        lin = dict(F=F, c=c, L=np.eye(2), W=np.diag([eps, wl.theta[0, 1]]), H=H, r=r, R=R)
+        wl2.lin = lin
+        wl2.y, wl2.dt, wl2.m0, wl2.P0 = wl.y, wl.dt, wl.m0, wl.P0
+        wl2.seg_off = wl.seg_off
+        vals.append(_dense.dense_least_squares(wl2, 0)[1])
+    assert abs(vals[1] - o["mstar"][0]) <= 1e-4 * abs(o["mstar"][0])
+    assert abs(vals[1] - o["mstar"][0]) < abs(vals[0] - o["mstar"][0])
+
+
+def test_torch_and_c_oracles_agree_on_batches():
+    wl = workloads.cv_batched(n_seg=5, lmin=3, lmax=6, seed=41)
+    o = cref.smooth(wl)
+    for s in range(wl.n_seg):
+        seg = ref.workload_segment(wl, s)
+        T = wl.seg_off[s + 1] - wl.seg_off[s]
+        r = ref.smooth_segment("cv", seg["theta"], torch.zeros(T + 1, 4, dtype=torch.float64),
+                               seg["dt"], seg["y"], seg["m0"], seg["P0"], 4)
+        st = wl.seg_states(s)
+        np.testing.assert_allclose(o["xs"][st], r["xs"].numpy(), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(o["P"][st], r["P"].numpy(), rtol=0, atol=1e-12)
+        assert abs(o["loglik"][s] - r["loglik"].item()) < 1e-10 * abs(o["loglik"][s])
+        assert abs(o["mstar"][s] - r["mstar"].item()) < 1e-10 * abs(o["mstar"][s])
+
+
+def test_filter_converges_to_dare():
+    """Long-run filter covariance equals the discrete algebraic Riccati
+    solution of the forward model (Phi, Phi dtQ Phi^T, H, R/dt)."""
+    wl = workloads.cv(T=20000, d=2, dt=1e-3, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                      P0=1e-2 * np.eye(4), seed=2)
+    o = cref.smooth(wl)
+    F, c, L, W, H, r, R = _dense.step_terms(wl, 0)
+    dt = 1e-3
+    Phi = np.linalg.inv(np.eye(4) - dt * F[0])
+    Qd = Phi @ (dt * L @ W @ L.T) @ Phi.T
+    Pp = scipy.linalg.solve_discrete_are(Phi.T, H[0].T, Qd, R / dt)
+    Hk = H[0]
+    Pf = Pp - Pp @ Hk.T @ np.linalg.solve(Hk @ Pp @ Hk.T + R / dt, Hk @ Pp)
+    assert np.abs(o["P"][-1] - Pf).max() <= 1e-10 * np.abs(Pf).max()
+
+
+def test_wiener_velocity_care_closed_form_first_order():
+    """Kalman--Bucy steady state of the Wiener velocity model (Sec. 2.5):
+    P_inf = [[sqrt2 q^1/4 r^3/4, sqrt(q r)], [sqrt(q r), sqrt2 q^3/4 r^1/4]].
+    The discrete filter reaches it with an O(dt) error."""
+    q, r = 1.0, 0.1
+    Pinf = np.array([[np.sqrt(2) * q ** 0.25 * r ** 0.75, np.sqrt(q * r)],
+                     [np.sqrt(q * r), np.sqrt(2) * q ** 0.75 * r ** 0.25]])
+    # the closed form itself solves the CARE F P + P F^T + Q - P H^T R^-1 H P = 0
+    Fm = np.array([[0.0, 1.0], [0.0, 0.0]])
+    Qm = np.diag([0.0, q])
+    Hm = np.array([[1.0, 0.0]])
+    res = Fm @ Pinf + Pinf @ Fm.T + Qm - Pinf @ Hm.T @ Hm @ Pinf / r
+    assert np.abs(res).max() < 1e-12
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        T = int(round(40.0 / dt))
+        wl = workloads.cv(T=T, d=1, dt=dt, q=q, r=r, seed=1)
+        o = cref.smooth(wl)
+        errs.append(np.abs(o["P"][-1] - Pinf).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+
+
+def _dense_ll_theta(wl, theta):
+    w = workloads.Workload(**{**wl.__dict__})
+    w.theta = theta[None]
+    return _dense.dense_posterior(w, 0)[2]
+
+
+def _dense_mstar_theta(wl, theta):
+    """M* = objective at the dense posterior mean (conditioning, not least
+    squares, so singular Q is fine); the objective is evaluated with the
+    driving-noise energy of the constrained step residuals."""
+    w = workloads.Workload(**{**wl.__dict__})
+    w.theta = theta[None]
+    mean, _, _ = _dense.dense_posterior(w, 0)
+    F, c, L, W, H, r, R = _dense.step_terms(w, 0)
+    dt = w.dt
+    d0 = mean[0] - w.m0[0]
+    M = 0.5 * d0 @ np.linalg.solve(w.P0[0], d0)
+    Lp = np.linalg.pinv(L)
+    for k in range(1, mean.shape[0]):
+        D = mean[k] - mean[k - 1] - dt[k - 1] * (F[k - 1] @ mean[k] + c[k - 1])
+        u = Lp @ D
+        e = w.y[:, k - 1] - H[k - 1] @ mean[k] - r[k - 1]
+        M += 0.5 * u @ np.linalg.solve(dt[k - 1] * W, u) + 0.5 * dt[k - 1] * e @ np.linalg.solve(R, e)
+    return M
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.6])
+def test_gradients_autograd_vs_dense_finite_differences(gamma):
+    """Oracle gradients (autograd of the KF/RTS definitions) against central
+    differences of the dense likelihood and of the dense objective value."""
+    wl = workloads.cv(T=30, d=2, dt=0.05, gamma=gamma, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                      P0=1e-2 * np.eye(4), seed=51)
+    seg = ref.workload_segment(wl, 0)
+    gl, gm, _ = ref.gradients("cv", 4, seg, torch.zeros(31, 4, dtype=torch.float64))
+    th = wl.theta[0].copy()
+    for i in range(3):
+        h = 1e-6 * max(1.0, abs(th[i]))
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd_l = (_dense_ll_theta(wl, tp) - _dense_ll_theta(wl, tm)) / (2 * h)
+        fd_m = (_dense_mstar_theta(wl, tp) - _dense_mstar_theta(wl, tm)) / (2 * h)
+        assert abs(gl[i].item() - fd_l) <= 1e-6 * max(1.0, abs(fd_l)), (i, gl[i].item(), fd_l)
+        assert abs(gm[i].item() - fd_m) <= 1e-6 * max(1.0, abs(fd_m)), (i, gm[i].item(), fd_m)
+
+
+def test_nonlinear_iteration_matches_nonlinear_least_squares():
+    """Gauss--Newton (Sec. 4.4) on Van der Pol (Q invertible) converges to the
+    minimiser of the nonlinear discretised objective found by a generic
+    trust-region least-squares solver, and the objective decreases."""
+    wl = workloads.vdp(T=60, dt=0.02, seed=61, n_iter=8)
+    seg = ref.workload_segment(wl, 0)
+    its, out = ref.gauss_newton("vdp", seg["theta"], seg["dt"], seg["y"], seg["m0"], seg["P0"],
+                                2, 8)
+    obj = [ref.map_objective_nonlinear("vdp", seg["theta"], x, seg["dt"], seg["y"], seg["m0"],
+                                       seg["P0"], 2).item() for x in its]
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(obj[1:], obj[2:]))
+    mu, q, rr = wl.theta[0]
+    T = wl.n_steps
+    dt = wl.dt[0]
+    y = wl.y[0]
+    P0i = np.linalg.cholesky(np.linalg.inv(wl.P0[0])).T
+
+    def resid(z):
+        x = z.reshape(T + 1, 2)
+        out = [P0i @ (x[0] - wl.m0[0])]
+        f = np.stack([x[1:, 1], mu * (1 - x[1:, 0] ** 2) * x[1:, 1] - x[1:, 0]], 1)
+        D = (x[1:] - x[:-1] - dt * f) / np.sqrt(dt * q)
+        E = (y - x[1:, 0]) * np.sqrt(dt / rr)
+        return np.concatenate([out[0], D.reshape(-1), E])
+
+    sol = scipy.optimize.least_squares(resid, its[-1].numpy().reshape(-1) + 0.01, xtol=1e-15,
+                                       ftol=1e-15, gtol=1e-15)
+    x_ls = sol.x.reshape(T + 1, 2)
+    assert np.abs(its[-1].numpy() - x_ls).max() < 1e-7 * np.abs(x_ls).max()
+    # stationarity of the nonlinear objective at the last iterate
+    x = its[-1].clone().requires_grad_(True)
+    M = ref.map_objective_nonlinear("vdp", seg["theta"], x, seg["dt"], seg["y"], seg["m0"],
+                                    seg["P0"], 2)
+    g, = torch.autograd.grad(M, x)
+    assert g.abs().max().item() < 1e-6
+
+
+def test_lorenz_iterates_c_and_torch_agree_and_decrease():
+    wl = workloads.lorenz63(n_seg=2, T=200, seed=71, n_iter=5)
+    o = cref.iterate(wl, keep_iterates=True)
+    for s in range(2):
+        seg = ref.workload_segment(wl, s)
+        its, out = ref.gauss_newton("lorenz63", seg["theta"], seg["dt"], seg["y"], seg["m0"],
+                                    seg["P0"], 3, 5)
+        st = wl.seg_states(s)
+        for i in range(5):
+            np.testing.assert_allclose(o["iterates"][i][:, st].T, its[i].numpy(), rtol=0,
+                                       atol=1e-9 * np.abs(its[i].numpy()).max())
+        obj = [ref.map_objective_nonlinear("lorenz63", seg["theta"], x, seg["dt"], seg["y"],
+                                           seg["m0"], seg["P0"], 3).item() for x in its]
+        assert obj[-1] <= obj[1]
