@@ -1,0 +1,186 @@
+/*
+ * mapscan: parallel-in-time MAP trajectory estimation for partially observed
+ * SDEs on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves, for every segment of a batch, the discretised
+ * Onsager--Machlup MAP problem of the model (Sec. 2.1, eq. statespace and
+ * eq. OM)
+ *
+ *     dx/dt = f(x) + L w,    y = h(x) + v,    w, v white noise with spectral
+ *     densities W and R,     x(t0) ~ N(m0, P0),
+ *
+ * in its linear-affine form (Sec. 2.4, eq. linear-statespace) or, for a
+ * nonlinear model, by iterated Taylor linearisation (Sec. 4.4).  One grid
+ * step [t_{k-1}, t_k] of length dt_k contributes the element of Sec. 4.2
+ * (eq. backwardLQT) obtained by one explicit-Euler step of its ODE from the
+ * boundary value; the drift and measurement are evaluated at the step's right
+ * end and y_k is the measurement of x_k.  The filter is the associative scan
+ * of Sec. 3.4 (eq. valueparallel) with the linear combination rule of Sec. 4.1;
+ * the trajectory is recovered by the affine scan of Sec. 4.3 (eq. 42), i.e. the
+ * parallel Kalman--Bucy filter in information form and the parallel RTS
+ * smoother (Sec. 2.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Real arrays have the dtype in map_problem.dtype (float or double);
+ *    per-segment scalar outputs (log-likelihood, objective, gradients) are
+ *    always double.
+ *  - Every array pointer is a DEVICE pointer owned by the caller, except
+ *    seg_off_host.  Nothing is allocated or freed by the library; the
+ *    workspace is caller-owned too (map_workspace_bytes, map_workspace_init).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*, NULL = the default stream).  A call returns after enqueueing.
+ *  - Steps of all segments are concatenated: segment s owns steps
+ *    seg_off[s] .. seg_off[s+1]-1 and states seg_off[s]+s .. seg_off[s+1]+s
+ *    (T_s steps give T_s+1 states; state seg_off[s]+s is the prior time t0).
+ *    n_states = n_steps + n_seg.
+ *  - Layout is structure-of-arrays: component c of item i is at
+ *    base[c * n + i] with n = n_steps for step-indexed arrays and n = n_states
+ *    for state-indexed arrays.  Symmetric nx x nx matrices are stored as
+ *    nx(nx+1)/2 planes, lower triangle in row order (0,0),(1,0),(1,1),(2,0)...
+ *  - Errors: every entry returns a map_status; arguments are validated on the
+ *    host before anything is launched, and a failing check launches nothing.
+ *    map_last_error() gives a readable message for the calling thread.
+ *  - One call at a time per workspace: calls that share a workspace must be
+ *    ordered on one stream.
+ */
+#ifndef MAPSCAN_H
+#define MAPSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAPSCAN_ABI_VERSION 1
+
+typedef enum {
+  MAP_OK = 0,
+  MAP_E_ARG = -1,         /* null/invalid pointer or value */
+  MAP_E_DIM = -2,         /* dimensions out of range or inconsistent */
+  MAP_E_DTYPE = -3,       /* unknown dtype */
+  MAP_E_LAYOUT = -4,      /* segment offsets not monotone / inconsistent */
+  MAP_E_NUMERIC = -5,     /* reserved: non-finite result detected */
+  MAP_E_HIP = -6,         /* a HIP runtime call or kernel launch failed */
+  MAP_E_WORKSPACE = -7,   /* workspace missing or too small */
+  MAP_E_UNSUPPORTED = -8  /* model/dimension combination not built */
+} map_status;
+
+typedef enum { MAP_F32 = 0, MAP_F64 = 1 } map_dtype;
+
+/* Models.  Parameter vectors theta (per segment):
+ *   MAP_MODEL_LINEAR    none; dense F, c, L, W, H, r, R given per step (forward only)
+ *   MAP_MODEL_CV        (gamma, q, r): F = [[0, I], [0, -gamma I]], c = 0, L = [0; I],
+ *                       W = q I, H = [I, 0], r = 0, R = r I; nx = 2d, ny = nw = d.
+ *                       With gamma = 0 this is the Wiener velocity model (Sec. 5.1).
+ *   MAP_MODEL_VDP       (mu, q, r): f = (x2, mu (1 - x1^2) x2 - x1), L = I, W = q I,
+ *                       h = x1, R = r; nx = 2, ny = 1, nw = 2.
+ *   MAP_MODEL_LORENZ63  (sigma, rho, beta, q, r): Lorenz-63 drift, L = I, W = q I,
+ *                       h = x, R = r I; nx = ny = nw = 3.
+ * Nonlinear models (VDP, LORENZ63) are linearised about map_problem.xbar. */
+typedef enum {
+  MAP_MODEL_LINEAR = 0,
+  MAP_MODEL_CV = 1,
+  MAP_MODEL_VDP = 2,
+  MAP_MODEL_LORENZ63 = 3
+} map_model;
+
+typedef struct {
+  int32_t nx, ny, nw;      /* state, measurement and driving-noise dimensions */
+  int32_t dtype;           /* map_dtype of every real input/output array */
+  int32_t model;           /* map_model */
+  int32_t n_theta;         /* must equal the model's parameter count (0 for LINEAR) */
+  int64_t n_seg;           /* number of trajectories, >= 1 */
+  int64_t n_steps;         /* total steps = seg_off[n_seg] */
+  const int64_t* seg_off;       /* device [n_seg+1]: 0 = seg_off[0] <= seg_off[1] <= ... */
+  const int64_t* seg_off_host;  /* optional host copy; when given it is validated */
+  const void* dt;          /* device: dt_k at dt[k * dt_stride], > 0 */
+  int64_t dt_stride;       /* 1 (per step) or 0 (one shared value) */
+  const void* y;           /* device [ny][n_steps]: y_k measures the state x_k */
+  const void* m0;          /* device [n_seg][nx] prior means (m0_stride = nx, or 0: shared) */
+  int64_t m0_stride;
+  const void* P0;          /* device [n_seg][nx*nx] row-major SPD prior covariances */
+  int64_t P0_stride;       /* nx*nx, or 0: shared */
+  const void* theta;       /* device [n_seg][n_theta] (theta_stride = n_theta, or 0: shared) */
+  int64_t theta_stride;
+  const void* xbar;        /* device [nx][n_states] linearisation states (nonlinear models) */
+  /* MAP_MODEL_LINEAR only: row-major per-step matrices F [nx*nx], c [nx],
+   * L [nx*nw], W [nw*nw] (SPD), H [ny*nx], r [ny], R [ny*ny] (SPD); matrix of
+   * step k at base + k * stride (stride 0: one matrix for all steps). */
+  const void *F, *c, *L, *W, *H, *r, *R;
+  int64_t F_stride, c_stride, L_stride, W_stride, H_stride, r_stride, R_stride;
+} map_problem;
+
+/* Size in bytes of the workspace every scan entry needs for this problem
+ * (0 if the problem is invalid; see map_last_error). */
+size_t map_workspace_bytes(const map_problem* p);
+
+/* Zero the workspace's control words.  Call once after allocating a
+ * workspace; every entry point leaves them zero when its kernels finish. */
+map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* Element build (Sec. 4.2, eq. backwardLQT, one explicit-Euler step from the
+ * boundary value; Sec. 3.4 for the prior element a_T = -log p(x(t0))):
+ * writes, for every state i, the element of the step ending at i -- or the
+ * prior element (A = 0, b = 0, C = 0, eta = P0^{-1} m0, J = P0^{-1}) at a
+ * segment's first state -- as planes
+ *   A (nx*nx, row-major), b (nx), C (sym), eta (nx), J (sym)
+ * i.e. [nx*nx + 2 nx + nx(nx+1)][n_states] in `elems`. */
+map_status map_build_elements(const map_problem* p, void* elems, void* stream);
+
+/* Filter scan (Sec. 3.4 eq. valueparallel with the combination rule of
+ * Sec. 4.1; information form of the Kalman--Bucy filter, Sec. 2.5):
+ *   S     out [nx(nx+1)/2][n_states]  information matrix S_k = P_k^{-1}
+ *   v     out [nx][n_states]          information vector v_k = P_k^{-1} m_k
+ *   m, P  optional out (NULL to skip) filter mean and covariance
+ *   loglik optional out [n_seg] (double): log p(y_1..y_T) by the
+ *         prediction-error decomposition of the same discrete model. */
+map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void* P,
+                           double* loglik, void* ws, size_t ws_bytes, void* stream);
+
+/* Trajectory scan (Sec. 4.3, eq. 42: x*_{k-1} = G_k x*_k + beta_k composed by an
+ * associative affine scan in reverse time order) from the filter's S, v:
+ *   xs    out [nx][n_states] MAP trajectory = smoothed means
+ *   Ps    optional out [nx(nx+1)/2][n_states] smoothed covariances
+ *   obj   optional out [n_seg] (double): the discretised OM objective (without
+ *         the divergence term) at xs. */
+map_status map_smoother_scan(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+                             double* obj, void* ws, size_t ws_bytes, void* stream);
+
+/* Filter and trajectory scans fused (the filter fix-up and the trajectory
+ * up-sweep share one pass), plus, when g_loglik / g_obj are given, the adjoint:
+ * gradients with respect to theta of the log-likelihood (Fisher identity) and
+ * of the objective's minimum (envelope theorem), [n_seg][n_theta] double.
+ * Gradients need a parametric model (not LINEAR) and Ps != NULL. */
+map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps, double* loglik,
+                      double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Iterated Taylor linearisation (Sec. 4.4): xbar^(0) = xbar0 (NULL: m0 of each
+ * segment at every state), then n_iter times: linearise about xbar, solve
+ * with map_smooth, xbar <- xs.  xbar_buf [nx][n_states] is caller scratch that
+ * holds the linearisation point of the last solve on return (p->xbar is
+ * ignored).  loglik, obj and the gradients refer to that last linear problem
+ * with its linearisation point held fixed. */
+map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const void* xbar0,
+                                  void* xbar_buf, void* S, void* v, void* xs, void* Ps,
+                                  double* loglik, double* obj, double* g_loglik, double* g_obj,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint from saved filter moments (checkpointing: elements and trajectory
+ * are recomputed, nothing else is stored): reverse-scans the same elements to
+ * rebuild xs and Ps (written to the caller's buffers) and accumulates
+ * g_loglik and g_obj ([n_seg][n_theta] double) as in map_smooth. */
+map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+                        double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
+                        void* stream);
+
+const char* map_last_error(void);
+int32_t map_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAPSCAN_H */

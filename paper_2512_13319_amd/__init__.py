@@ -1,0 +1,288 @@
+"""mapscan: parallel-in-time continuous-time MAP trajectory estimation on
+MI355X (gfx950).
+
+Thin Python layer over the C-ABI library `libmapscan.so` (include/mapscan.h):
+it owns device memory through torch, passes raw pointers and the current HIP
+stream, and wraps the fused scans in a `torch.autograd.Function`.  Every step
+of the computation runs in the library's HIP kernels; there is no fallback,
+so a missing library raises.
+
+Layouts (see include/mapscan.h): state-indexed outputs are [components,
+n_states] planes; symmetric matrices are nx(nx+1)/2 lower-triangle planes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MapError, MODELS
+
+__all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
+           "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
+           "MapError", "N_THETA"]
+
+N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def sym_to_full(planes: torch.Tensor, nx: int) -> torch.Tensor:
+    """[nx(nx+1)/2, n] lower-triangle planes -> [n, nx, nx]."""
+    n = planes.shape[1]
+    out = planes.new_empty((n, nx, nx))
+    c = 0
+    for r in range(nx):
+        for q in range(r + 1):
+            out[:, r, q] = planes[c]
+            out[:, q, r] = planes[c]
+            c += 1
+    return out
+
+
+class Problem:
+    """A batch of trajectories of one model, resident on the GPU.
+
+    model     "cv" | "vdp" | "lorenz63" | "linear"
+    seg_off   int64 [n_seg+1] step offsets (host array or tensor)
+    dt        [n_steps] step lengths (or a 0-d tensor / float for a shared value)
+    y         [ny, n_steps] measurements
+    m0, P0    [n_seg, nx], [n_seg, nx, nx] (or [nx], [nx, nx] shared)
+    theta     [n_seg, n_theta] (or [n_theta] shared) model parameters
+    xbar      [nx, n_states] linearisation states (nonlinear models)
+    lin       dict of F, c, L, W, H, r, R for the linear model: each either one
+              matrix or a leading per-step axis
+    """
+
+    def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
+                 dtype=torch.float64, device="cuda"):
+        _lib.load()
+        self.model, self.nx, self.ny, self.nw = model, nx, ny, nw
+        self.dtype, self.device = dtype, torch.device(device)
+        t = lambda a: None if a is None else torch.as_tensor(a).to(self.device, dtype).contiguous()
+        so = np.ascontiguousarray(np.asarray(seg_off if not torch.is_tensor(seg_off)
+                                             else seg_off.cpu().numpy(), dtype=np.int64))
+        self.seg_off_host = so
+        self.seg_off = torch.as_tensor(so).to(self.device)
+        self.n_seg = int(so.shape[0] - 1)
+        self.n_steps = int(so[-1])
+        self.n_states = self.n_steps + self.n_seg
+        dt_t = t(dt)
+        self.dt = dt_t.reshape(-1)
+        self.y = t(y).reshape(ny, self.n_steps) if self.n_steps > 0 else t(np.zeros((ny, 1)))
+        m0 = t(m0)
+        P0 = t(P0)
+        self.m0 = m0.reshape(-1, nx)
+        self.P0 = P0.reshape(-1, nx, nx)
+        self.n_theta = N_THETA[model]
+        self.theta = None if theta is None else t(theta).reshape(-1, self.n_theta)
+        self.xbar = None if xbar is None else t(xbar).reshape(nx, self.n_states)
+        self.lin = None
+        if lin is not None:
+            self.lin = {}
+            shapes = dict(F=(nx, nx), c=(nx,), L=(nx, nw), W=(nw, nw), H=(ny, nx), r=(ny,),
+                          R=(ny, ny))
+            for k, shp in shapes.items():
+                a = t(lin[k])
+                per_step = a.dim() == len(shp) + 1
+                self.lin[k] = (a, int(np.prod(shp)) if per_step else 0)
+        self._ws = None
+        self._sync_struct()
+
+    # ------------------------------------------------------------------ marshalling
+    def _sync_struct(self):
+        s = _lib.MapProblem()
+        s.nx, s.ny, s.nw = self.nx, self.ny, self.nw
+        s.dtype = _lib.MAP_F64 if self.dtype == torch.float64 else _lib.MAP_F32
+        s.model = MODELS[self.model]
+        s.n_theta = self.n_theta
+        s.n_seg, s.n_steps = self.n_seg, self.n_steps
+        s.seg_off = self.seg_off.data_ptr()
+        s.seg_off_host = self.seg_off_host.ctypes.data
+        s.dt = self.dt.data_ptr()
+        s.dt_stride = 0 if self.dt.numel() == 1 else 1
+        s.y = self.y.data_ptr()
+        s.m0 = self.m0.data_ptr()
+        s.m0_stride = 0 if self.m0.shape[0] == 1 else self.nx
+        s.P0 = self.P0.data_ptr()
+        s.P0_stride = 0 if self.P0.shape[0] == 1 else self.nx * self.nx
+        if self.theta is not None:
+            s.theta = self.theta.data_ptr()
+            s.theta_stride = 0 if self.theta.shape[0] == 1 else self.n_theta
+        if self.xbar is not None:
+            s.xbar = self.xbar.data_ptr()
+        if self.lin is not None:
+            for k in ("F", "c", "L", "W", "H", "r", "R"):
+                a, st = self.lin[k]
+                setattr(s, k, a.data_ptr())
+                setattr(s, k + "_stride", st)
+        self.struct = s
+
+    def set_xbar(self, xbar):
+        self.xbar = xbar.to(self.device, self.dtype).reshape(self.nx, self.n_states).contiguous()
+        self._sync_struct()
+
+    def set_theta(self, theta):
+        self.theta = theta.to(self.device, self.dtype).reshape(-1, self.n_theta).contiguous()
+        self._sync_struct()
+
+    def workspace(self):
+        lib = _lib.load()
+        nbytes = lib.map_workspace_bytes(ctypes.byref(self.struct))
+        if nbytes == 0:
+            raise MapError(-2, lib.map_last_error().decode())
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _lib.check(lib.map_workspace_init(_ptr(self._ws), nbytes, _stream()))
+        return self._ws
+
+    # ------------------------------------------------------------------ allocation helpers
+    @property
+    def nsym(self):
+        return self.nx * (self.nx + 1) // 2
+
+    def _empty(self, *shape, dtype=None):
+        return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
+
+
+def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None):
+    """Device-resident Problem from a `workloads.Workload`-like object."""
+    return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
+                   theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
+                   lin=getattr(wl, "lin", None), dtype=dtype, device=device)
+
+
+def build_elements(p: Problem):
+    lib = _lib.load()
+    n = p.nx * p.nx + 2 * p.nx + 2 * p.nsym
+    out = p._empty(n, p.n_states)
+    _lib.check(lib.map_build_elements(ctypes.byref(p.struct), _ptr(out), _stream()))
+    return out
+
+
+def filter_scan(p: Problem, moments=False, loglik=True):
+    lib = _lib.load()
+    ws = p.workspace()
+    S = p._empty(p.nsym, p.n_states)
+    v = p._empty(p.nx, p.n_states)
+    m = p._empty(p.nx, p.n_states) if moments else None
+    P = p._empty(p.nsym, p.n_states) if moments else None
+    ll = p._empty(p.n_seg, dtype=torch.float64) if loglik else None
+    _lib.check(lib.map_filter_scan(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(m), _ptr(P),
+                                   _ptr(ll), _ptr(ws), ws.numel(), _stream()))
+    return dict(S=S, v=v, m=m, P=P, loglik=ll)
+
+
+def smoother_scan(p: Problem, S, v, covariances=True, objective=True):
+    lib = _lib.load()
+    ws = p.workspace()
+    xs = p._empty(p.nx, p.n_states)
+    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    obj = p._empty(p.n_seg, dtype=torch.float64) if objective else None
+    _lib.check(lib.map_smoother_scan(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs),
+                                     _ptr(Ps), _ptr(obj), _ptr(ws), ws.numel(), _stream()))
+    return dict(xs=xs, Ps=Ps, obj=obj)
+
+
+def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False, out=None):
+    """Fused filter + trajectory scans (+ adjoint when grad).  `out` may carry
+    preallocated buffers (same keys as the result) to avoid allocations."""
+    lib = _lib.load()
+    ws = p.workspace()
+    o = out or {}
+    S = o.get("S") if o.get("S") is not None else p._empty(p.nsym, p.n_states)
+    v = o.get("v") if o.get("v") is not None else p._empty(p.nx, p.n_states)
+    xs = o.get("xs") if o.get("xs") is not None else p._empty(p.nx, p.n_states)
+    Ps = (o.get("Ps") if o.get("Ps") is not None else p._empty(p.nsym, p.n_states)) \
+        if covariances else None
+    f64 = torch.float64
+    ll = (o.get("loglik") if o.get("loglik") is not None else p._empty(p.n_seg, dtype=f64)) \
+        if loglik else None
+    obj = (o.get("obj") if o.get("obj") is not None else p._empty(p.n_seg, dtype=f64)) \
+        if objective else None
+    gl = gm = None
+    if grad:
+        gl = o.get("g_loglik") if o.get("g_loglik") is not None else p._empty(p.n_seg, p.n_theta, dtype=f64)
+        gm = o.get("g_obj") if o.get("g_obj") is not None else p._empty(p.n_seg, p.n_theta, dtype=f64)
+    _lib.check(lib.map_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
+                              _ptr(ll), _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
+                              _stream()))
+    return dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm)
+
+
+def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, loglik=True,
+                       objective=True, grad=False):
+    lib = _lib.load()
+    ws = p.workspace()
+    f64 = torch.float64
+    xb = p._empty(p.nx, p.n_states)
+    S = p._empty(p.nsym, p.n_states)
+    v = p._empty(p.nx, p.n_states)
+    xs = p._empty(p.nx, p.n_states)
+    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    ll = p._empty(p.n_seg, dtype=f64) if loglik else None
+    obj = p._empty(p.n_seg, dtype=f64) if objective else None
+    gl = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
+    gm = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
+    x0 = None if xbar0 is None else xbar0.to(p.device, p.dtype).contiguous()
+    _lib.check(lib.map_iterated_nonlinear(ctypes.byref(p.struct), int(n_iter), _ptr(x0), _ptr(xb),
+                                          _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps), _ptr(ll),
+                                          _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
+                                          _stream()))
+    return dict(xbar=xb, S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm)
+
+
+def backward(p: Problem, S, v, covariances=True, objective=True):
+    """Adjoint from saved filter moments: recomputes the trajectory and returns
+    d loglik / d theta and d obj / d theta per segment."""
+    lib = _lib.load()
+    ws = p.workspace()
+    f64 = torch.float64
+    xs = p._empty(p.nx, p.n_states)
+    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    obj = p._empty(p.n_seg, dtype=f64) if objective else None
+    gl = p._empty(p.n_seg, p.n_theta, dtype=f64)
+    gm = p._empty(p.n_seg, p.n_theta, dtype=f64)
+    _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
+                                _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(), _stream()))
+    return dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm)
+
+
+class MapSmooth(torch.autograd.Function):
+    """(theta) -> (xs, loglik, obj) for a parametric model.
+
+    The forward pass runs the fused scans with the adjoint enabled, so the
+    gradients of loglik (Fisher identity) and obj (envelope theorem) with
+    respect to theta come out of the same pass; backward scales them by the
+    incoming cotangents.  A cotangent on xs (implicit-function VJP) is not
+    provided and raises."""
+
+    @staticmethod
+    def forward(ctx, theta, problem: Problem):
+        problem.set_theta(theta.detach())
+        r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True)
+        ctx.save_for_backward(r["g_loglik"], r["g_obj"])
+        ctx.theta_shape = theta.shape
+        ctx.theta_dtype = theta.dtype
+        ctx.mark_non_differentiable(r["xs"])
+        return r["xs"], r["loglik"], r["obj"]
+
+    @staticmethod
+    def backward(ctx, g_xs, g_ll, g_obj):
+        gl, gm = ctx.saved_tensors
+        g = torch.zeros_like(gl)
+        if g_ll is not None:
+            g = g + g_ll[:, None] * gl
+        if g_obj is not None:
+            g = g + g_obj[:, None] * gm
+        if ctx.theta_shape != g.shape:
+            g = g.sum(0) if len(ctx.theta_shape) == 1 else g
+        return g.to(ctx.theta_dtype).reshape(ctx.theta_shape), None

@@ -1,0 +1,7 @@
+// Instantiations: general linear model, nx = 4.
+#include "runner_impl.h"
+namespace ms {
+MS_INSTANTIATE(ModelLinear<4 MS_COMMA 2 MS_COMMA 2>)
+MS_INSTANTIATE(ModelLinear<4 MS_COMMA 2 MS_COMMA 4>)
+MS_INSTANTIATE(ModelLinear<4 MS_COMMA 4 MS_COMMA 4>)
+}  // namespace ms

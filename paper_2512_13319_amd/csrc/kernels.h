@@ -1,0 +1,1004 @@
+// Scan kernels for gfx950.
+//
+// Work decomposition (all passes): the flat sequence of states of all
+// segments (segment s owns states seg_off[s]+s .. seg_off[s+1]+s) is cut into
+// chunks of L consecutive states, one chunk per lane; a 64-lane wavefront is a
+// tile; a 256-thread block holds four independent tiles.
+//
+//   pass A  (filter up-sweep)     each lane folds its chunk's elements into one
+//           element; a Hillis-Steele scan over the wavefront gives every lane
+//           its exclusive in-tile prefix (stored); lane 63's inclusive value is
+//           the tile aggregate (stored).  The block that finishes last scans
+//           the tile aggregates and stores one (S, v) carry per tile.
+//   pass B  (filter fix-up, fused with the trajectory up-sweep)  each lane
+//           applies tile carry and in-tile prefix to get (S, v) before its
+//           chunk, runs the information step through its chunk writing S_k,
+//           v_k (and on request m_k, P_k and the prediction-error terms of the
+//           log-likelihood), and with the same factorisation builds the
+//           trajectory maps (G, beta, Lam) of its states and folds them.  A
+//           reverse Hillis-Steele scan and a last-block reverse tile scan give
+//           the value (x, P) after every tile.
+//   pass C  (trajectory fix-up)   each lane gets (x, P) after its chunk and
+//           walks backwards writing x*_k and P^s_k; the adjoint terms of the
+//           log-likelihood and of the objective are accumulated on the way.
+//
+// Segment boundaries need no flags: a segment's first state carries the prior
+// element (A = 0, C = 0), which cuts every run that contains it, and a
+// segment's last state carries the constant trajectory map (0, S^{-1} v,
+// S^{-1}), which cuts the reverse scan.
+#pragma once
+#include "elements.h"
+
+namespace ms {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+template <int N> struct Sym { static constexpr int n = N * (N + 1) / 2; };
+template <int N> struct ElemSz { static constexpr int n = N * N + 2 * N + 2 * Sym<N>::n; };
+template <int N> struct AffSz { static constexpr int n = N * N + N + Sym<N>::n; };
+
+// --------------------------------------------------------------------------- SoA I/O
+// A "plane set" stores component c of item i at base[c * ld + i].
+template <typename T, int N>
+MS_DEVONLY void store_sym(T* base, int64_t ld, int64_t i, const T (&a)[N][N], int c0 = 0) {
+  int c = c0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) base[(c++) * ld + i] = a[r][q];
+}
+template <typename T, int N>
+MS_DEVONLY void load_sym(const T* base, int64_t ld, int64_t i, T (&a)[N][N], int c0 = 0) {
+  int c = c0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) {
+      a[r][q] = base[(c++) * ld + i];
+      a[q][r] = a[r][q];
+    }
+}
+template <typename T, int N>
+MS_DEVONLY void store_vec(T* base, int64_t ld, int64_t i, const T (&a)[N], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) base[(c0 + r) * ld + i] = a[r];
+}
+template <typename T, int N>
+MS_DEVONLY void load_vec(const T* base, int64_t ld, int64_t i, T (&a)[N], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) a[r] = base[(c0 + r) * ld + i];
+}
+template <typename T, int N, int M>
+MS_DEVONLY void store_mat(T* base, int64_t ld, int64_t i, const T (&a)[N][M], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < M; ++q) base[(c0 + r * M + q) * ld + i] = a[r][q];
+}
+template <typename T, int N, int M>
+MS_DEVONLY void load_mat(const T* base, int64_t ld, int64_t i, T (&a)[N][M], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < M; ++q) a[r][q] = base[(c0 + r * M + q) * ld + i];
+}
+
+// element planes: A (N*N), b (N), C (sym), eta (N), J (sym)
+template <typename T, int N>
+MS_DEVONLY void store_elem(T* base, int64_t ld, int64_t i, const Elem<T, N>& e) {
+  store_mat(base, ld, i, e.A, 0);
+  store_vec(base, ld, i, e.b, N * N);
+  store_sym(base, ld, i, e.C, N * N + N);
+  store_vec(base, ld, i, e.eta, N * N + N + Sym<N>::n);
+  store_sym(base, ld, i, e.J, N * N + 2 * N + Sym<N>::n);
+}
+template <typename T, int N>
+MS_DEVONLY void load_elem(const T* base, int64_t ld, int64_t i, Elem<T, N>& e) {
+  load_mat(base, ld, i, e.A, 0);
+  load_vec(base, ld, i, e.b, N * N);
+  load_sym(base, ld, i, e.C, N * N + N);
+  load_vec(base, ld, i, e.eta, N * N + N + Sym<N>::n);
+  load_sym(base, ld, i, e.J, N * N + 2 * N + Sym<N>::n);
+}
+template <typename T, int N>
+MS_DEVONLY void store_aff(T* base, int64_t ld, int64_t i, const Aff<T, N>& a) {
+  store_mat(base, ld, i, a.Phi, 0);
+  store_vec(base, ld, i, a.bt, N * N);
+  store_sym(base, ld, i, a.Om, N * N + N);
+}
+template <typename T, int N>
+MS_DEVONLY void load_aff(const T* base, int64_t ld, int64_t i, Aff<T, N>& a) {
+  load_mat(base, ld, i, a.Phi, 0);
+  load_vec(base, ld, i, a.bt, N * N);
+  load_sym(base, ld, i, a.Om, N * N + N);
+}
+
+template <typename T, int N>
+MS_DEVONLY void shfl_elem(Elem<T, N>& o, const Elem<T, N>& e, int src) {
+  shfl_mat(o.A, e.A, src);
+  shfl_vec(o.b, e.b, src);
+  shfl_sym(o.C, e.C, src);
+  shfl_vec(o.eta, e.eta, src);
+  shfl_sym(o.J, e.J, src);
+}
+template <typename T, int N>
+MS_DEVONLY void shfl_aff(Aff<T, N>& o, const Aff<T, N>& a, int src) {
+  shfl_mat(o.Phi, a.Phi, src);
+  shfl_vec(o.bt, a.bt, src);
+  shfl_sym(o.Om, a.Om, src);
+}
+
+// --------------------------------------------------------------------------- workspace
+// Pointers into the caller's workspace; sizes fixed by (n_states, L, N).
+template <typename T>
+struct Ws {
+  unsigned int* counters;  // [4], zero between launches
+  T* lane_pre;             // [ElemSz][n_lanes]   exclusive in-tile filter prefix per lane
+  T* tile_agg;             // [ElemSz][n_tiles]
+  T* tile_carry;           // [Sym + N][n_tiles]  (S, v) before each tile
+  T* slane_pre;            // [AffSz][n_lanes]    trajectory map from after the lane's chunk to tile end
+  T* stile_agg;            // [AffSz][n_tiles]
+  T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
+  int64_t n_lanes, n_tiles;
+};
+
+// Per-segment accumulators (double): loglik [n_seg], obj [n_seg],
+// g_loglik [n_seg][NTH], g_obj [n_seg][NTH].
+struct Acc {
+  double* loglik;
+  double* obj;
+  double* g_loglik;
+  double* g_obj;
+};
+
+// --------------------------------------------------------------------------- model access
+template <typename T, class M>
+struct Cursor {
+  static constexpr int NX = M::NX, NY = M::NY, NW = M::NW;
+  static constexpr int NTH_ = M::NTH > 0 ? M::NTH : 1;
+  int64_t s;          // current segment
+  int64_t head;       // its first state
+  int64_t next_head;  // first state of the next segment (n_states after the last)
+  T th[NTH_];
+
+  MS_DEVONLY void load_seg(const Prob<T>& p) {
+    head = p.seg_off[s] + s;
+    next_head = p.seg_off[s + 1] + s + 1;
+    if constexpr (M::NTH > 0) {
+#pragma unroll
+      for (int t = 0; t < M::NTH; ++t) th[t] = p.theta[s * p.th_stride + t];
+    }
+  }
+  // segment containing state i (0 <= i < n_states)
+  MS_DEVONLY void init(const Prob<T>& p, int64_t i) {
+    int64_t lo = 0, hi = p.n_seg - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (p.seg_off[mid] + mid <= i) lo = mid; else hi = mid - 1;
+    }
+    s = lo;
+    load_seg(p);
+  }
+  MS_DEVONLY void next(const Prob<T>& p) { ++s; load_seg(p); }
+  MS_DEVONLY void prev(const Prob<T>& p) { --s; load_seg(p); }
+  MS_DEVONLY bool is_head(int64_t i) const { return i == head; }
+  MS_DEVONLY bool is_last(int64_t i) const { return i + 1 == next_head; }
+
+  // Model terms and measurement of the step that ends at (non-head) state i.
+  MS_DEVONLY void step(const Prob<T>& p, int64_t i, Step<T, NX, NY, NW>& st, T (&y)[NY]) const {
+    const int64_t k = i - s - 1;  // step index
+    const T dt = p.dt[k * p.dt_stride];
+#pragma unroll
+    for (int c = 0; c < NY; ++c) y[c] = p.y[c * p.n_steps + k];
+    if constexpr (M::NTH > 0) {
+      T xb[NX];
+      if constexpr (M::kNonlinear) {
+#pragma unroll
+        for (int c = 0; c < NX; ++c) xb[c] = p.xbar[c * p.n_states + i];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NX; ++c) xb[c] = T(0);
+      }
+      M::terms(th, xb, dt, st);
+    } else {
+      st.dt = dt;
+      const T* F = p.F + k * p.sF;
+      const T* c = p.c + k * p.sc;
+      const T* L = p.L + k * p.sL;
+      const T* W = p.W + k * p.sW;
+      const T* H = p.H + k * p.sH;
+      const T* r = p.r + k * p.sr;
+      const T* R = p.R + k * p.sR;
+#pragma unroll
+      for (int a = 0; a < NX; ++a) {
+#pragma unroll
+        for (int b = 0; b < NX; ++b) st.F[a][b] = F[a * NX + b];
+        st.c[a] = c[a];
+      }
+      T Wm[NW][NW], Lw[NW][NW], dw[NW], Lm[NX][NW];
+#pragma unroll
+      for (int a = 0; a < NW; ++a)
+#pragma unroll
+        for (int b = 0; b < NW; ++b) Wm[a][b] = W[a * NW + b];
+      chol(Wm, Lw, dw);
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NW; ++b) Lm[a][b] = L[a * NW + b];
+      mm(Lm, Lw, st.V);
+      const T sd = sqrt_(dt);
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NW; ++b) st.V[a][b] *= sd;
+#pragma unroll
+      for (int a = 0; a < NY; ++a) {
+#pragma unroll
+        for (int b = 0; b < NX; ++b) st.H[a][b] = H[a * NX + b];
+        st.r[a] = r[a];
+#pragma unroll
+        for (int b = 0; b < NY; ++b) st.R[a][b] = R[a * NY + b];
+      }
+      spd_inv(st.R, st.Rinv);
+    }
+  }
+
+  MS_DEVONLY void xbar(const Prob<T>& p, int64_t i, T (&xb)[NX]) const {
+    if constexpr (M::kNonlinear) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) xb[c] = p.xbar[c * p.n_states + i];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) xb[c] = T(0);
+    }
+  }
+
+  // prior of the current segment: S0 = P0^{-1}, v0 = P0^{-1} m0
+  MS_DEVONLY void prior(const Prob<T>& p, T (&S0)[NX][NX], T (&v0)[NX], T (&m0)[NX],
+                        T (&P0i)[NX][NX]) const {
+    T P0[NX][NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+      m0[a] = p.m0[s * p.m0_stride + a];
+#pragma unroll
+      for (int b = 0; b < NX; ++b) P0[a][b] = p.P0[s * p.P0_stride + a * NX + b];
+    }
+    spd_inv(P0, P0i);
+    mcopy(P0i, S0);
+    mv(P0i, m0, v0);
+  }
+};
+
+// --------------------------------------------------------------------------- reductions
+// Segmented sum over the lanes of a wavefront (segment ids non-decreasing
+// with the lane index), then one atomic per run.  seg < 0 marks no data.
+template <int K>
+MS_DEVONLY void flush_wave(int64_t seg, double (&val)[K], double* const (&dst)[K],
+                           const int64_t (&stride)[K]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sg = int(seg);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int src = lane + d < kWave ? lane + d : lane;
+    const int so = shfl(sg, src);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      double o = shfl(val[t], src);
+      if (lane + d < kWave && so == sg) val[t] += o;
+    }
+  }
+  const int sp = shfl(sg, lane > 0 ? lane - 1 : 0);
+  if (sg >= 0 && (lane == 0 || sp != sg)) {
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if (dst[t]) unsafeAtomicAdd(dst[t] + sg * stride[t], val[t]);
+  }
+}
+
+template <int K>
+MS_DEVONLY void flush_lane(int64_t seg, double (&val)[K], double* const (&dst)[K],
+                           const int64_t (&stride)[K]) {
+  if (seg < 0) return;
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    if (dst[t]) unsafeAtomicAdd(dst[t] + seg * stride[t], val[t]);
+    val[t] = 0.0;
+  }
+}
+
+// --------------------------------------------------------------------------- last block
+MS_DEVONLY bool arrive_last(unsigned int* counter) {
+  __shared__ unsigned int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+MS_DEVONLY void release_counter(unsigned int* counter) {
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Filter tile scan, run by the last block: (S, v) before every tile.
+template <typename T, int N>
+MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
+  __shared__ T s_w[4][ElemSz<N>::n];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  const int64_t nt = ws.n_tiles;
+  const int64_t K = (nt + kBlock - 1) / kBlock;
+  const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
+  Elem<T, N> acc, tmp, o;
+  elem_identity(acc);
+  for (int64_t t = t0; t < t1; ++t) {
+    load_elem(ws.tile_agg, nt, t, o);
+    combine(acc, o, tmp);
+    acc = tmp;
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    shfl_elem(o, acc, lane >= d ? lane - d : lane);
+    if (lane >= d) {
+      combine(o, acc, tmp);
+      acc = tmp;
+    }
+  }
+  if (lane == kWave - 1) {
+    T* w = s_w[wv];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) w[c++] = acc.A[r][q];
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[c++] = acc.b[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) w[c++] = acc.C[r][q];
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[c++] = acc.eta[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) w[c++] = acc.J[r][q];
+  }
+  __syncthreads();
+  // exclusive prefix of the lane: waves before, then lanes before
+  Elem<T, N> lx;
+  shfl_elem(lx, acc, lane > 0 ? lane - 1 : 0);
+  if (lane == 0) elem_identity(lx);
+  T S[N][N], v[N];
+  mzero(S);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = T(0);
+  for (int w = 0; w < wv; ++w) {
+    const T* s = s_w[w];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) o.A[r][q] = s[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r) o.b[r] = s[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) { o.C[r][q] = s[c++]; o.C[q][r] = o.C[r][q]; }
+#pragma unroll
+    for (int r = 0; r < N; ++r) o.eta[r] = s[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) { o.J[r][q] = s[c++]; o.J[q][r] = o.J[r][q]; }
+    carry_apply(S, v, o);
+  }
+  carry_apply(S, v, lx);
+  for (int64_t t = t0; t < t1; ++t) {
+    store_sym(ws.tile_carry, nt, t, S, 0);
+    store_vec(ws.tile_carry, nt, t, v, Sym<N>::n);
+    load_elem(ws.tile_agg, nt, t, o);
+    carry_apply(S, v, o);
+  }
+}
+
+// Trajectory tile scan, run by the last block: (x, P) after every tile.
+template <typename T, int N>
+MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
+  __shared__ T s_w[4][AffSz<N>::n];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  const int64_t nt = ws.n_tiles;
+  const int64_t K = (nt + kBlock - 1) / kBlock;
+  const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
+  Aff<T, N> acc, o;
+  aff_identity(acc);
+  for (int64_t t = t0; t < t1; ++t) {
+    load_aff(ws.stile_agg, nt, t, o);
+    aff_append(acc, o);
+  }
+  // reverse inclusive scan: acc <- acc o (lanes to the right)
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    shfl_aff(o, acc, lane + d < kWave ? lane + d : lane);
+    if (lane + d < kWave) aff_append(acc, o);
+  }
+  if (lane == 0) {
+    T* w = s_w[wv];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) w[c++] = acc.Phi[r][q];
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[c++] = acc.bt[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) w[c++] = acc.Om[r][q];
+  }
+  __syncthreads();
+  Aff<T, N> ex;  // lanes to the right within the wave, then waves to the right
+  shfl_aff(ex, acc, lane + 1 < kWave ? lane + 1 : lane);
+  if (lane == kWave - 1) aff_identity(ex);
+  for (int w = wv + 1; w < 4; ++w) {
+    const T* s = s_w[w];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) o.Phi[r][q] = s[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r) o.bt[r] = s[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) { o.Om[r][q] = s[c++]; o.Om[q][r] = o.Om[r][q]; }
+    aff_append(ex, o);
+  }
+  // the composition to the end of the sequence is a constant map (it contains
+  // the last state), so its offset is the value after this thread's tiles
+  T x[N], P[N][N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) x[r] = ex.bt[r];
+  mcopy(ex.Om, P);
+  for (int64_t t = t1 - 1; t >= t0; --t) {
+    store_vec(ws.stile_carry, nt, t, x, 0);
+    store_sym(ws.stile_carry, nt, t, P, N);
+    load_aff(ws.stile_agg, nt, t, o);
+    aff_apply(o, x, P);
+  }
+}
+
+// --------------------------------------------------------------------------- pass A
+template <typename T, class M, int L>
+__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
+  constexpr int N = M::NX;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t tile = g >> 6;
+  const int64_t j0 = g * L;
+  Elem<T, N> agg;
+  elem_identity(agg);
+  if (j0 < p.n_states) {
+    Cursor<T, M> cur;
+    cur.init(p, j0);
+    for (int t = 0; t < L; ++t) {
+      const int64_t i = j0 + t;
+      if (i >= p.n_states) break;
+      if (cur.is_head(i)) {
+        T m0[N], P0i[N][N];
+        cur.prior(p, agg.J, agg.eta, m0, P0i);
+        mzero(agg.A);
+        mzero(agg.C);
+#pragma unroll
+        for (int r = 0; r < N; ++r) agg.b[r] = T(0);
+      } else {
+        Step<T, N, M::NY, M::NW> st;
+        T y[M::NY];
+        cur.step(p, i, st, y);
+        Fresh<T, N, M::NW> f;
+        fresh_from_step(st, y, f);
+        fold_fresh(agg, f);
+      }
+      if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
+    }
+  }
+  // in-tile inclusive scan
+  Elem<T, N> o, tmp;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    shfl_elem(o, agg, lane >= d ? lane - d : lane);
+    if (lane >= d) {
+      combine(o, agg, tmp);
+      agg = tmp;
+    }
+  }
+  shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
+  if (lane == 0) elem_identity(o);
+  if (g < ws.n_lanes) store_elem(ws.lane_pre, ws.n_lanes, g, o);
+  if (lane == kWave - 1 && tile < ws.n_tiles) store_elem(ws.tile_agg, ws.n_tiles, tile, agg);
+  if (arrive_last(ws.counters + 0)) {
+    filter_tile_scan<T, N>(ws);
+    release_counter(ws.counters + 0);
+  }
+}
+
+// --------------------------------------------------------------------------- pass B
+enum : int { kModeFilter = 0, kModeFused = 1, kModeTrajOnly = 2 };
+
+struct FilterOut {
+  void* S;    // [Sym][n_states]
+  void* v;    // [N][n_states]
+  void* m;    // optional [N][n_states]
+  void* P;    // optional [Sym][n_states]
+  int want_loglik;
+};
+
+// log N(y; H m^- + r, H P^- H^T + R/dt) with P^- = Sp^{-1}, m^- = Sp^{-1} vp
+template <typename T, int N, int NY, int NW>
+MS_DEVONLY double pred_loglik(const T (&Sp)[N][N], const T (&vp)[N], const Step<T, N, NY, NW>& st,
+                              const T (&y)[NY]) {
+  T Ls[N][N], ds[N];
+  chol(Sp, Ls, ds);
+  T mp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) mp[i] = vp[i];
+  trsv_lower(Ls, ds, mp);
+  trsv_upper_t(Ls, ds, mp);
+  T X[N][NY];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < NY; ++j) X[i][j] = st.H[j][i];
+  trsm_lower(Ls, ds, X);
+  T Sg[NY][NY];
+  mtm_sym(X, X, Sg);
+  const T idt = rcp(st.dt);
+#pragma unroll
+  for (int i = 0; i < NY; ++i)
+#pragma unroll
+    for (int j = 0; j < NY; ++j) Sg[i][j] += st.R[i][j] * idt;
+  T Hm[NY], e[NY];
+  mv(st.H, mp, Hm);
+#pragma unroll
+  for (int i = 0; i < NY; ++i) e[i] = y[i] - st.r[i] - Hm[i];
+  T Lg[NY][NY], dg[NY];
+  chol(Sg, Lg, dg);
+  trsv_lower(Lg, dg, e);
+  double q = 0.0, det = 1.0;
+#pragma unroll
+  for (int i = 0; i < NY; ++i) {
+    q += double(e[i]) * double(e[i]);
+    det *= double(Lg[i][i]);
+  }
+  return -0.5 * (double(NY) * 1.8378770664093453 + 2.0 * ::log(det) + q);
+}
+
+template <typename T, class M, int L, int kMode>
+__global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, FilterOut fo, Acc acc) {
+  constexpr int N = M::NX, NY = M::NY, NW = M::NW;
+  constexpr bool kFilter = kMode != kModeTrajOnly;
+  constexpr bool kTraj = kMode != kModeFilter;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t tile = g >> 6;
+  const int64_t j0 = g * L;
+  const int64_t ns = p.n_states;
+  T* So = static_cast<T*>(fo.S);
+  T* vo = static_cast<T*>(fo.v);
+  T* mo = static_cast<T*>(fo.m);
+  T* Po = static_cast<T*>(fo.P);
+  T S[N][N], v[N];
+  if constexpr (kFilter) {
+    if (tile < ws.n_tiles) {
+      load_sym(ws.tile_carry, ws.n_tiles, tile, S, 0);
+      load_vec(ws.tile_carry, ws.n_tiles, tile, v, Sym<N>::n);
+      Elem<T, N> lp;
+      load_elem(ws.lane_pre, ws.n_lanes, g, lp);
+      carry_apply(S, v, lp);
+    }
+  }
+  Aff<T, N> sagg;
+  aff_identity(sagg);
+  double ll = 0.0;
+  int64_t seg_acc = -1;
+  if (j0 < ns) {
+    Cursor<T, M> cur;
+    cur.init(p, j0);
+    seg_acc = cur.s;
+    for (int t = 0; t < L; ++t) {
+      const int64_t i = j0 + t;
+      if (i >= ns) break;
+      if constexpr (kFilter) {
+        if (cur.is_head(i)) {
+          if (kTraj && t > 0) {
+            // previous state ends its segment: constant trajectory map
+            T G[N][N], beta[N], Lam[N][N];
+            mzero(G);
+            spd_inv(S, Lam);
+            mv(Lam, v, beta);
+            aff_append(sagg, G, beta, Lam);
+          }
+          if (fo.want_loglik && seg_acc != cur.s) {
+            double* d[1] = {acc.loglik};
+            const int64_t sd[1] = {1};
+            double val[1] = {ll};
+            flush_lane<1>(seg_acc, val, d, sd);
+            ll = 0.0;
+            seg_acc = cur.s;
+          }
+          T m0[N], P0i[N][N];
+          cur.prior(p, S, v, m0, P0i);
+        } else {
+          Step<T, N, NY, NW> st;
+          T y[NY];
+          cur.step(p, i, st, y);
+          Fresh<T, N, NW> f;
+          fresh_from_step(st, y, f);
+          T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
+          if (kTraj && t > 0) {
+            info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
+            aff_append(sagg, G, beta, Lam);
+          } else {
+            info_step<T, N, NW, false>(S, v, f, Sn, vn, Sp, G, beta, Lam);
+          }
+          if (fo.want_loglik) {
+            T vp[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) vp[r] = vn[r] - f.eta[r];
+            ll += pred_loglik(Sp, vp, st, y);
+          }
+          mcopy(Sn, S);
+#pragma unroll
+          for (int r = 0; r < N; ++r) v[r] = vn[r];
+        }
+        store_sym(So, ns, i, S);
+        store_vec(vo, ns, i, v);
+        if (mo != nullptr) {
+          T Pm[N][N], mm_[N];
+          spd_inv(S, Pm);
+          mv(Pm, v, mm_);
+          store_vec(mo, ns, i, mm_);
+          store_sym(Po, ns, i, Pm);
+        }
+      } else {
+        // trajectory maps from stored filter moments
+        load_sym(So, ns, i, S);
+        load_vec(vo, ns, i, v);
+        if (t > 0) {
+          // handled below with the element of state i
+        }
+      }
+      if constexpr (!kFilter) {
+        // map of state i needs the element of state i+1
+        if (cur.is_last(i)) {
+          T G[N][N], beta[N], Lam[N][N];
+          mzero(G);
+          spd_inv(S, Lam);
+          mv(Lam, v, beta);
+          aff_append(sagg, G, beta, Lam);
+        } else {
+          Step<T, N, NY, NW> st;
+          T y[NY];
+          cur.step(p, i + 1, st, y);
+          Fresh<T, N, NW> f;
+          fresh_from_step(st, y, f);
+          T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
+          info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
+          aff_append(sagg, G, beta, Lam);
+        }
+      }
+      if (cur.is_last(i) && i + 1 < ns) cur.next(p);
+    }
+    if constexpr (kFilter && kTraj) {
+      // trajectory map of the chunk's last state
+      const int64_t il = min<int64_t>(j0 + L, ns) - 1;
+      if (il + 1 >= ns || il + 1 == cur.head) {
+        T G[N][N], beta[N], Lam[N][N];
+        mzero(G);
+        spd_inv(S, Lam);
+        mv(Lam, v, beta);
+        aff_append(sagg, G, beta, Lam);
+      } else {
+        Step<T, N, NY, NW> st;
+        T y[NY];
+        cur.step(p, il + 1, st, y);
+        Fresh<T, N, NW> f;
+        fresh_from_step(st, y, f);
+        T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
+        info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
+        aff_append(sagg, G, beta, Lam);
+      }
+    }
+  }
+  if constexpr (kFilter) {
+    if (fo.want_loglik) {
+      double* d[1] = {acc.loglik};
+      const int64_t sd[1] = {1};
+      double val[1] = {ll};
+      flush_wave<1>(seg_acc, val, d, sd);
+    }
+  }
+  if constexpr (kTraj) {
+    // reverse in-tile scan of the trajectory maps
+    Aff<T, N> o;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      shfl_aff(o, sagg, lane + d < kWave ? lane + d : lane);
+      if (lane + d < kWave) aff_append(sagg, o);
+    }
+    shfl_aff(o, sagg, lane + 1 < kWave ? lane + 1 : lane);
+    if (lane == kWave - 1) aff_identity(o);
+    if (g < ws.n_lanes) store_aff(ws.slane_pre, ws.n_lanes, g, o);
+    if (lane == 0 && tile < ws.n_tiles) store_aff(ws.stile_agg, ws.n_tiles, tile, sagg);
+    if (arrive_last(ws.counters + 1)) {
+      traj_tile_scan<T, N>(ws);
+      release_counter(ws.counters + 1);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------- pass C
+struct TrajOut {
+  const void* S;
+  const void* v;
+  void* xs;   // [N][n_states]
+  void* Ps;   // optional [Sym][n_states]
+  int want_obj;
+  int want_grad;
+};
+
+template <typename T, class M, int L, bool kGrad>
+__global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajOut to, Acc acc) {
+  constexpr int N = M::NX, NY = M::NY, NW = M::NW;
+  constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
+  constexpr int KV = 1 + 2 * NTH;
+  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t tile = g >> 6;
+  const int64_t j0 = g * L;
+  const int64_t ns = p.n_states;
+  const T* Si = static_cast<const T*>(to.S);
+  const T* vi = static_cast<const T*>(to.v);
+  T* xo = static_cast<T*>(to.xs);
+  T* Po = static_cast<T*>(to.Ps);
+  T x[N], P[N][N];
+  if (tile < ws.n_tiles) {
+    load_vec(ws.stile_carry, ws.n_tiles, tile, x, 0);
+    load_sym(ws.stile_carry, ws.n_tiles, tile, P, N);
+    Aff<T, N> lp;
+    load_aff(ws.slane_pre, ws.n_lanes, g, lp);
+    aff_apply(lp, x, P);
+  }
+  double val[KV];
+#pragma unroll
+  for (int t = 0; t < KV; ++t) val[t] = 0.0;
+  double* dst[KV];
+  int64_t dstr[KV];
+  dst[0] = to.want_obj ? acc.obj : nullptr;
+  dstr[0] = 1;
+#pragma unroll
+  for (int t = 0; t < NTH; ++t) {
+    dst[1 + t] = (kGrad && M::NTH > 0) ? acc.g_loglik + t : nullptr;
+    dst[1 + NTH + t] = (kGrad && M::NTH > 0) ? acc.g_obj + t : nullptr;
+    dstr[1 + t] = dstr[1 + NTH + t] = NTH;
+  }
+  int64_t seg_acc = -1;
+  if (j0 < ns) {
+    const int64_t il = min<int64_t>(j0 + L, ns) - 1;
+    Cursor<T, M> cur;
+    cur.init(p, il);
+    seg_acc = cur.s;
+    for (int64_t i = il; i >= j0; --i) {
+      T S[N][N], v[N];
+      load_sym(Si, ns, i, S);
+      load_vec(vi, ns, i, v);
+      if (cur.is_last(i)) {
+        spd_inv(S, P);
+        mv(P, v, x);
+      } else {
+        Step<T, N, NY, NW> st;
+        T y[NY];
+        cur.step(p, i + 1, st, y);
+        Fresh<T, N, NW> f;
+        fresh_from_step(st, y, f);
+        // trajectory map of state i (shares Z with the information step)
+        T W[N][NW];
+        mm(S, f.V, W);
+        T Z[NW][NW];
+        mtm_sym(f.V, W, Z);
+#pragma unroll
+        for (int a = 0; a < NW; ++a) Z[a][a] += T(1);
+        T Lz[NW][NW], dz[NW];
+        chol(Z, Lz, dz);
+        T X[NW][N];
+        mtm(W, f.A, X);
+        trsm_lower(Lz, dz, X);
+        trsm_upper_t(Lz, dz, X);
+        T G[N][N], VX[N][N];
+        mm(f.V, X, VX);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b) G[a][b] = f.A[a][b] - VX[a][b];
+        T bc[N], beta[N];
+        {
+          T z[NW];
+          mtv(f.V, v, z);
+          mv(f.V, z, bc);
+#pragma unroll
+          for (int a = 0; a < N; ++a) bc[a] += f.b[a];
+          mtv(W, bc, z);
+          trsv_lower(Lz, dz, z);
+          trsv_upper_t(Lz, dz, z);
+          T vz[N];
+          mv(f.V, z, vz);
+#pragma unroll
+          for (int a = 0; a < N; ++a) beta[a] = bc[a] - vz[a];
+        }
+        T Yv[NW][N], Lam[N][N];
+#pragma unroll
+        for (int a = 0; a < NW; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b) Yv[a][b] = f.V[b][a];
+        trsm_lower(Lz, dz, Yv);
+        mtm_sym(Yv, Yv, Lam);
+        // x, P currently hold state i+1
+        T xn[N], Pn[N][N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) xn[a] = x[a];
+        mcopy(P, Pn);
+        traj_step(G, beta, Lam, x, P);
+        if (to.want_obj || kGrad) {
+          // costate lambda = v_i - S_i x*_i
+          T Sx[N], lam[N];
+          mv(S, x, Sx);
+#pragma unroll
+          for (int a = 0; a < N; ++a) lam[a] = v[a] - Sx[a];
+          T vl[NW];
+          mtv(f.V, lam, vl);
+          double ob = 0.0;
+#pragma unroll
+          for (int a = 0; a < NW; ++a) ob += 0.5 * double(vl[a]) * double(vl[a]);
+          // measurement of state i+1
+          T Hx[NY], eps[NY];
+          mv(st.H, xn, Hx);
+#pragma unroll
+          for (int a = 0; a < NY; ++a) eps[a] = y[a] - st.r[a] - Hx[a];
+          T Re[NY];
+          mv(st.Rinv, eps, Re);
+#pragma unroll
+          for (int a = 0; a < NY; ++a) ob += 0.5 * double(st.dt) * double(eps[a]) * double(Re[a]);
+          val[0] += ob;
+          if constexpr (kGrad && M::NTH > 0) {
+            // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T
+            T Yw[NW][N], Nm[N][N];
+#pragma unroll
+            for (int a = 0; a < NW; ++a)
+#pragma unroll
+              for (int b = 0; b < N; ++b) Yw[a][b] = W[b][a];
+            trsm_lower(Lz, dz, Yw);
+            mtm_sym(Yw, Yw, Nm);
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+              for (int b = 0; b < N; ++b) Nm[a][b] = S[a][b] - Nm[a][b];
+            T NA[N][N], NAP[N][N], E2[N][N];
+            mm(Nm, f.A, NA);
+            mm(NA, Pn, NAP);
+            mmt_sym(NAP, NA, E2);  // Nm A P^s A^T Nm
+            T Ainv[N][N];
+            inv(f.A, Ainv);
+            T GAl[N][N], GAm[N][N], GCl[N][N], GCm[N][N], Gbl[N], Gbm[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+              Gbl[a] = lam[a];
+              Gbm[a] = -lam[a];
+#pragma unroll
+              for (int b = 0; b < N; ++b) {
+                const T lx = lam[a] * xn[b];
+                GAl[a][b] = lx - NAP[a][b] + Ainv[b][a];
+                GAm[a][b] = -lx;
+                const T ll_ = lam[a] * lam[b];
+                GCl[a][b] = T(0.5) * (ll_ + E2[a][b] - Nm[a][b]);
+                GCm[a][b] = T(-0.5) * ll_;
+              }
+            }
+            // measurement: R-cotangents
+            T HP[NY][N], HPH[NY][NY];
+            mm(st.H, Pn, HP);
+            mmt_sym(HP, st.H, HPH);
+            T GRl[NY][NY], GRm[NY][NY];
+#pragma unroll
+            for (int a = 0; a < NY; ++a)
+#pragma unroll
+              for (int b = 0; b < NY; ++b) {
+                T sRe = Re[a] * Re[b];
+                T t2[1];
+                t2[0] = T(0);
+#pragma unroll
+                for (int c = 0; c < NY; ++c)
+#pragma unroll
+                  for (int d = 0; d < NY; ++d) t2[0] += st.Rinv[a][c] * HPH[c][d] * st.Rinv[d][b];
+                GRl[a][b] = T(-0.5) * st.Rinv[a][b] + T(0.5) * st.dt * (sRe + t2[0]);
+                GRm[a][b] = T(-0.5) * st.dt * sRe;
+              }
+            T xb[N];
+            cur.xbar(p, i + 1, xb);
+            double gl[NTH], gm[NTH];
+#pragma unroll
+            for (int t = 0; t < NTH; ++t) gl[t] = gm[t] = 0.0;
+            M::vjp(cur.th, xb, st.dt, GAl, Gbl, GCl, GRl, gl);
+            M::vjp(cur.th, xb, st.dt, GAm, Gbm, GCm, GRm, gm);
+#pragma unroll
+            for (int t = 0; t < NTH; ++t) {
+              val[1 + t] += gl[t];
+              val[1 + NTH + t] += gm[t];
+            }
+          }
+        }
+      }
+      store_vec(xo, ns, i, x);
+      if (Po != nullptr) store_sym(Po, ns, i, P);
+      if (cur.is_head(i)) {
+        if (to.want_obj) {
+          T S0[N][N], v0[N], m0[N], P0i[N][N];
+          cur.prior(p, S0, v0, m0, P0i);
+          T dlt[N], Pd[N];
+#pragma unroll
+          for (int a = 0; a < N; ++a) dlt[a] = x[a] - m0[a];
+          mv(P0i, dlt, Pd);
+          double ob = 0.0;
+#pragma unroll
+          for (int a = 0; a < N; ++a) ob += 0.5 * double(dlt[a]) * double(Pd[a]);
+          val[0] += ob;
+        }
+        if (i > j0) {
+          flush_lane<KV>(seg_acc, val, dst, dstr);
+          cur.prev(p);
+          seg_acc = cur.s;
+        }
+      }
+    }
+  }
+  if (to.want_obj || kGrad) flush_wave<KV>(seg_acc, val, dst, dstr);
+}
+
+// --------------------------------------------------------------------------- misc
+template <typename T, class M>
+__global__ void __launch_bounds__(kBlock) k_build_elements(Prob<T> p, T* out) {
+  constexpr int N = M::NX;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= p.n_states) return;
+  Cursor<T, M> cur;
+  cur.init(p, i);
+  Elem<T, N> e;
+  if (cur.is_head(i)) {
+    T m0[N], P0i[N][N];
+    cur.prior(p, e.J, e.eta, m0, P0i);
+    mzero(e.A);
+    mzero(e.C);
+#pragma unroll
+    for (int r = 0; r < N; ++r) e.b[r] = T(0);
+  } else {
+    Step<T, N, M::NY, M::NW> st;
+    T y[M::NY];
+    cur.step(p, i, st, y);
+    Fresh<T, N, M::NW> f;
+    fresh_from_step(st, y, f);
+    fresh_to_elem(f, e);
+  }
+  store_elem(out, p.n_states, i, e);
+}
+
+static __global__ void __launch_bounds__(kBlock) k_zero(double* a, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    a[i] = 0.0;
+}
+
+}  // namespace ms

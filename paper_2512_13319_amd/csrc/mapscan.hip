@@ -1,0 +1,300 @@
+// C-ABI front end: host-side validation, dispatch to the (dtype, model)
+// instantiation, error reporting.  Nothing here allocates device memory.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "models.h"
+#include "runner.h"
+
+namespace ms {
+
+__global__ void k_clear_words(unsigned int* w, int n) {
+  if (int(threadIdx.x) < n) w[threadIdx.x] = 0u;
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+map_status fail(map_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+map_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MAP_OK;
+  return fail(MAP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Models built into this library: (model, nx, ny, nw, n_theta).
+struct Entry {
+  int model, nx, ny, nw, nth;
+};
+
+#define MS_MODELS(X)                              \
+  X(MAP_MODEL_CV, 2, 1, 1, 3, ModelCV<1>)         \
+  X(MAP_MODEL_CV, 4, 2, 2, 3, ModelCV<2>)         \
+  X(MAP_MODEL_CV, 6, 3, 3, 3, ModelCV<3>)         \
+  X(MAP_MODEL_VDP, 2, 1, 2, 3, ModelVdP)          \
+  X(MAP_MODEL_LORENZ63, 3, 3, 3, 5, ModelLorenz63) \
+  X(MAP_MODEL_LINEAR, 1, 1, 1, 0, ModelLinear<1 MS_COMMA 1 MS_COMMA 1>) \
+  X(MAP_MODEL_LINEAR, 2, 1, 1, 0, ModelLinear<2 MS_COMMA 1 MS_COMMA 1>) \
+  X(MAP_MODEL_LINEAR, 2, 1, 2, 0, ModelLinear<2 MS_COMMA 1 MS_COMMA 2>) \
+  X(MAP_MODEL_LINEAR, 2, 2, 2, 0, ModelLinear<2 MS_COMMA 2 MS_COMMA 2>) \
+  X(MAP_MODEL_LINEAR, 3, 2, 2, 0, ModelLinear<3 MS_COMMA 2 MS_COMMA 2>) \
+  X(MAP_MODEL_LINEAR, 3, 2, 3, 0, ModelLinear<3 MS_COMMA 2 MS_COMMA 3>) \
+  X(MAP_MODEL_LINEAR, 3, 3, 3, 0, ModelLinear<3 MS_COMMA 3 MS_COMMA 3>) \
+  X(MAP_MODEL_LINEAR, 4, 2, 2, 0, ModelLinear<4 MS_COMMA 2 MS_COMMA 2>) \
+  X(MAP_MODEL_LINEAR, 4, 2, 4, 0, ModelLinear<4 MS_COMMA 2 MS_COMMA 4>) \
+  X(MAP_MODEL_LINEAR, 4, 4, 4, 0, ModelLinear<4 MS_COMMA 4 MS_COMMA 4>)
+#define MS_COMMA ,
+
+// Calls f.template run<T, M>() for the matching instantiation.
+template <class Fn>
+map_status dispatch(const map_problem& p, Fn&& f) {
+#define MS_CASE(MODEL, NX, NY, NW, NTH, M)                                            \
+  if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) {                   \
+    if (p.dtype == MAP_F64) return f.template run<double, M>();                       \
+    return f.template run<float, M>();                                                \
+  }
+  MS_MODELS(MS_CASE)
+#undef MS_CASE
+  return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
+              p.nx, p.ny, p.nw);
+}
+
+int model_ntheta(const map_problem& p) {
+#define MS_NTH(MODEL, NX, NY, NW, NTH, M) \
+  if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) return NTH;
+  MS_MODELS(MS_NTH)
+#undef MS_NTH
+  return -1;
+}
+
+bool model_nonlinear(int model) { return model == MAP_MODEL_VDP || model == MAP_MODEL_LORENZ63; }
+
+map_status validate(const map_problem* pp, bool need_xbar = true) {
+  if (pp == nullptr) return fail(MAP_E_ARG, "problem is NULL");
+  const map_problem& p = *pp;
+  if (p.dtype != MAP_F32 && p.dtype != MAP_F64) return fail(MAP_E_DTYPE, "unknown dtype %d", p.dtype);
+  if (p.nx < 1 || p.nx > 8 || p.ny < 1 || p.ny > 8 || p.nw < 1 || p.nw > 8)
+    return fail(MAP_E_DIM, "dimensions (nx, ny, nw) = (%d, %d, %d) outside [1, 8]", p.nx, p.ny, p.nw);
+  if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_LORENZ63)
+    return fail(MAP_E_ARG, "unknown model %d", p.model);
+  const int nth = model_ntheta(p);
+  if (nth < 0)
+    return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
+                p.nx, p.ny, p.nw);
+  if (p.n_theta != nth) return fail(MAP_E_DIM, "n_theta = %d, model needs %d", p.n_theta, nth);
+  if (p.n_seg < 1) return fail(MAP_E_DIM, "n_seg = %lld < 1", (long long)p.n_seg);
+  if (p.n_steps < 0) return fail(MAP_E_DIM, "n_steps < 0");
+  if (p.n_steps + p.n_seg > (int64_t(1) << 31) * 64)
+    return fail(MAP_E_DIM, "too many states");
+  if (p.seg_off == nullptr) return fail(MAP_E_ARG, "seg_off is NULL");
+  if (p.seg_off_host != nullptr) {
+    if (p.seg_off_host[0] != 0) return fail(MAP_E_LAYOUT, "seg_off[0] != 0");
+    for (int64_t s = 0; s < p.n_seg; ++s)
+      if (p.seg_off_host[s + 1] < p.seg_off_host[s])
+        return fail(MAP_E_LAYOUT, "seg_off decreases at segment %lld", (long long)s);
+    if (p.seg_off_host[p.n_seg] != p.n_steps)
+      return fail(MAP_E_LAYOUT, "seg_off[n_seg] = %lld != n_steps = %lld",
+                  (long long)p.seg_off_host[p.n_seg], (long long)p.n_steps);
+  }
+  if (p.dt == nullptr) return fail(MAP_E_ARG, "dt is NULL");
+  if (p.dt_stride != 0 && p.dt_stride != 1) return fail(MAP_E_ARG, "dt_stride must be 0 or 1");
+  if (p.n_steps > 0 && p.y == nullptr) return fail(MAP_E_ARG, "y is NULL");
+  if (p.m0 == nullptr || p.P0 == nullptr) return fail(MAP_E_ARG, "m0/P0 is NULL");
+  if (p.m0_stride < 0 || p.P0_stride < 0 || p.theta_stride < 0)
+    return fail(MAP_E_ARG, "negative stride");
+  if (nth > 0 && p.theta == nullptr) return fail(MAP_E_ARG, "theta is NULL");
+  if (need_xbar && model_nonlinear(p.model) && p.xbar == nullptr)
+    return fail(MAP_E_ARG, "nonlinear model needs xbar");
+  if (p.model == MAP_MODEL_LINEAR) {
+    const void* ptrs[7] = {p.F, p.c, p.L, p.W, p.H, p.r, p.R};
+    const int64_t strides[7] = {p.F_stride, p.c_stride, p.L_stride, p.W_stride,
+                                p.H_stride, p.r_stride, p.R_stride};
+    for (int i = 0; i < 7; ++i) {
+      if (ptrs[i] == nullptr) return fail(MAP_E_ARG, "linear model matrix %d is NULL", i);
+      if (strides[i] < 0) return fail(MAP_E_ARG, "negative stride for matrix %d", i);
+    }
+  }
+  return MAP_OK;
+}
+
+map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
+  const size_t need = ws_layout(p.nx, p.n_steps + p.n_seg, p.dtype == MAP_F64 ? 8 : 4).total;
+  if (ws == nullptr) return fail(MAP_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need)
+    return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return MAP_OK;
+}
+
+struct DoBuild {
+  const map_problem& p;
+  void* elems;
+  hipStream_t st;
+  template <typename T, class M> map_status run() {
+    return hip_status(Runner<T, M>::build(p, elems, st), "map_build_elements");
+  }
+};
+struct DoFilter {
+  const map_problem& p;
+  SmoothArgs a;
+  template <typename T, class M> map_status run() {
+    return hip_status(Runner<T, M>::filter(p, a), "map_filter_scan");
+  }
+};
+struct DoSmoother {
+  const map_problem& p;
+  SmoothArgs a;
+  bool grad;
+  template <typename T, class M> map_status run() {
+    return hip_status(Runner<T, M>::smoother(p, a, grad), grad ? "map_backward" : "map_smoother_scan");
+  }
+};
+struct DoSmooth {
+  const map_problem& p;
+  SmoothArgs a;
+  template <typename T, class M> map_status run() {
+    return hip_status(Runner<T, M>::smooth(p, a), "map_smooth");
+  }
+};
+struct DoInitX {
+  const map_problem& p;
+  void* xb;
+  hipStream_t st;
+  template <typename T, class M> map_status run() {
+    return hip_status(Runner<T, M>::init_xbar(p, xb, st), "map_iterated_nonlinear");
+  }
+};
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+size_t map_workspace_bytes(const map_problem* p) {
+  if (validate(p, false) != MAP_OK) return 0;
+  return ws_layout(p->nx, p->n_steps + p->n_seg, p->dtype == MAP_F64 ? 8 : 4).total;
+}
+
+map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+  if (ws == nullptr || ws_bytes < 256) return fail(MAP_E_WORKSPACE, "workspace too small");
+  k_clear_words<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(static_cast<unsigned int*>(ws), 64);
+  return hip_status(hipGetLastError(), "map_workspace_init");
+}
+
+map_status map_build_elements(const map_problem* p, void* elems, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (elems == nullptr) return fail(MAP_E_ARG, "elems is NULL");
+  return dispatch(*p, DoBuild{*p, elems, static_cast<hipStream_t>(stream)});
+}
+
+map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void* P, double* loglik,
+                           void* ws, size_t ws_bytes, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr) return fail(MAP_E_ARG, "S/v is NULL");
+  if ((m == nullptr) != (P == nullptr)) return fail(MAP_E_ARG, "m and P must be given together");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
+               static_cast<hipStream_t>(stream)};
+  return dispatch(*p, DoFilter{*p, a});
+}
+
+map_status map_smoother_scan(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+                             double* obj, void* ws, size_t ws_bytes, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
+               nullptr, nullptr, ws, static_cast<hipStream_t>(stream)};
+  return dispatch(*p, DoSmoother{*p, a, false});
+}
+
+map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps, double* loglik,
+                      double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
+                      void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
+    return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
+               static_cast<hipStream_t>(stream)};
+  return dispatch(*p, DoSmooth{*p, a});
+}
+
+map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const void* xbar0,
+                                  void* xbar_buf, void* S, void* v, void* xs, void* Ps,
+                                  double* loglik, double* obj, double* g_loglik, double* g_obj,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  map_status s = validate(p, false);
+  if (s != MAP_OK) return s;
+  if (n_iter < 1) return fail(MAP_E_ARG, "n_iter must be >= 1");
+  if (xbar_buf == nullptr || S == nullptr || v == nullptr || xs == nullptr)
+    return fail(MAP_E_ARG, "xbar_buf/S/v/xs is NULL");
+  if (xbar_buf == xs) return fail(MAP_E_ARG, "xbar_buf must not alias xs");
+  if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
+    return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t ns = p->n_steps + p->n_seg;
+  const size_t bytes = size_t(p->nx) * size_t(ns) * (p->dtype == MAP_F64 ? 8 : 4);
+  // iteration i reads xbar from `src` and writes xs to the other buffer; the
+  // last iteration must read xbar_buf and write xs
+  void* bufs[2] = {xbar_buf, xs};
+  int cur = ((n_iter - 1) % 2 == 0) ? 0 : 1;
+  if (xbar0 != nullptr) {
+    s = hip_status(hipMemcpyAsync(bufs[cur], xbar0, bytes, hipMemcpyDeviceToDevice, st),
+                   "map_iterated_nonlinear");
+    if (s != MAP_OK) return s;
+  } else {
+    s = dispatch(*p, DoInitX{*p, bufs[cur], st});
+    if (s != MAP_OK) return s;
+  }
+  map_problem q = *p;
+  for (int32_t it = 0; it < n_iter; ++it) {
+    const bool last = it == n_iter - 1;
+    q.xbar = bufs[cur];
+    SmoothArgs a{S, v, nullptr, nullptr, bufs[1 - cur], last ? Ps : nullptr,
+                 last ? loglik : nullptr, last ? obj : nullptr, last ? g_loglik : nullptr,
+                 last ? g_obj : nullptr, ws, st};
+    s = dispatch(q, DoSmooth{q, a});
+    if (s != MAP_OK) return s;
+    cur = 1 - cur;
+  }
+  return MAP_OK;
+}
+
+map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+                        double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
+                        void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if (g_loglik == nullptr || g_obj == nullptr) return fail(MAP_E_ARG, "g_loglik/g_obj is NULL");
+  if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
+               g_loglik, g_obj, ws, static_cast<hipStream_t>(stream)};
+  return dispatch(*p, DoSmoother{*p, a, true});
+}
+
+const char* map_last_error(void) { return g_err.c_str(); }
+
+int32_t map_abi_version(void) { return MAPSCAN_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Model functors: the per-step terms of the linear-affine problem solved at
+// one Gauss--Newton iteration (Sec. 2.4 eq. linear-statespace, linearised as
+// in Sec. 4.4), and the parameter cotangents needed by the adjoint.
+//
+// A step k covers [t_{k-1}, t_k]; every term is evaluated at the right end,
+// i.e. at the nominal state xbar_k of the state the step leads to.  From the
+// terms the scan element of the step is one explicit-Euler step of the
+// element ODE (Sec. 4.2, eq. backwardLQT, with the sign of the Q J term in
+// the A equation read as +) from its boundary value (I, 0, 0, 0, 0):
+//
+//   A = I - dt F,  b = -dt c,  C = dt L W L^T = V V^T,
+//   J = dt H^T R^{-1} H,  eta = dt H^T R^{-1} (y - r).
+//
+// Models hand out V = sqrt(dt) L chol(W) instead of C, so that every solve
+// against a fresh element is a small SPD system.
+#pragma once
+#include "linalg.h"
+
+namespace ms {
+
+template <typename T, int NX, int NY, int NW>
+struct Step {
+  T dt;
+  T F[NX][NX];
+  T c[NX];
+  T V[NX][NW];     // C = V V^T = dt L W L^T
+  T H[NY][NX];
+  T r[NY];
+  T R[NY][NY];     // measurement spectral density
+  T Rinv[NY][NY];
+};
+
+// Device-side view of the problem (all pointers device memory).
+template <typename T>
+struct Prob {
+  int64_t n_seg, n_steps, n_states;
+  const int64_t* seg_off;  // [n_seg+1] step offsets
+  const T* dt;             // [n_steps] or one scalar (dt_stride 0)
+  int64_t dt_stride;
+  const T* y;              // [ny][n_steps]
+  const T* m0;             // [n_seg][nx] (stride 0: shared)
+  int64_t m0_stride;
+  const T* P0;             // [n_seg][nx][nx] row-major (stride 0: shared)
+  int64_t P0_stride;
+  const T* theta;          // [n_seg][n_theta] (stride 0: shared)
+  int64_t th_stride;
+  const T* xbar;           // [nx][n_states] linearisation states (nonlinear models)
+  // general linear model: row-major per-step matrices, stride 0 = shared by all steps
+  const T *F, *c, *L, *W, *H, *r, *R;
+  int64_t sF, sc, sL, sW, sH, sr, sR;
+};
+
+// ------------------------------------------------------------------ constant velocity
+// theta = (gamma, q, r): F = [[0, I], [0, -gamma I]], L = [0; I], W = q I,
+// H = [I, 0], R = r I.  nx = 2D.  With gamma = 0 and D = 2 this is the
+// Wiener velocity model of the paper's linear experiment (Sec. 5.1).
+template <int D>
+struct ModelCV {
+  static constexpr int NX = 2 * D, NY = D, NW = D, NTH = 3;
+  static constexpr bool kNonlinear = false;
+  static constexpr bool kAdjoint = true;
+
+  template <typename T>
+  static MS_DEV void terms(const T* th, const T (&)[NX], T dt, Step<T, NX, NY, NW>& s) {
+    const T g = th[0], q = th[1], rr = th[2];
+    s.dt = dt;
+    mzero(s.F);
+    mzero(s.V);
+    mzero(s.H);
+    mzero(s.R);
+    mzero(s.Rinv);
+    const T sv = sqrt_(dt * q);
+    const T ri = rcp(rr);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      s.F[i][D + i] = T(1);
+      s.F[D + i][D + i] = -g;
+      s.V[D + i][i] = sv;
+      s.H[i][i] = T(1);
+      s.R[i][i] = rr;
+      s.Rinv[i][i] = ri;
+      s.r[i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) s.c[i] = T(0);
+  }
+
+  // theta-cotangent of the element parameters: A = I - dt F(theta),
+  // b = -dt c, C = dt q L L^T, R = r I.
+  template <typename T>
+  static MS_DEV void vjp(const T* th, const T (&)[NX], T dt, const T (&GA)[NX][NX],
+                         const T (&)[NX], const T (&GC)[NX][NX], const T (&GR)[NY][NY],
+                         double (&out)[NTH]) {
+    (void)th;
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      a += double(GA[D + i][D + i]);
+      b += double(GC[D + i][D + i]);
+      c += double(GR[i][i]);
+    }
+    out[0] += double(dt) * a;  // dA/dgamma = dt on the velocity block
+    out[1] += double(dt) * b;  // dC/dq = dt L L^T
+    out[2] += c;               // dR/dr = I
+  }
+};
+
+// ------------------------------------------------------------------ Van der Pol
+// theta = (mu, q, r): f = (x2, mu (1 - x1^2) x2 - x1), L = I, W = q I, h = x1, R = r.
+struct ModelVdP {
+  static constexpr int NX = 2, NY = 1, NW = 2, NTH = 3;
+  static constexpr bool kNonlinear = true;
+  static constexpr bool kAdjoint = true;
+
+  template <typename T>
+  static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {
+    const T mu = th[0], q = th[1], rr = th[2];
+    const T x1 = x[0], x2 = x[1];
+    s.dt = dt;
+    s.F[0][0] = T(0);
+    s.F[0][1] = T(1);
+    s.F[1][0] = T(-2) * mu * x1 * x2 - T(1);
+    s.F[1][1] = mu * (T(1) - x1 * x1);
+    // c = f(x) - F x
+    const T f1 = mu * (T(1) - x1 * x1) * x2 - x1;
+    s.c[0] = x2 - x2;
+    s.c[1] = f1 - (s.F[1][0] * x1 + s.F[1][1] * x2);
+    const T sv = sqrt_(dt * q);
+    s.V[0][0] = sv;
+    s.V[0][1] = T(0);
+    s.V[1][0] = T(0);
+    s.V[1][1] = sv;
+    s.H[0][0] = T(1);
+    s.H[0][1] = T(0);
+    s.r[0] = T(0);
+    s.R[0][0] = rr;
+    s.Rinv[0][0] = rcp(rr);
+  }
+
+  template <typename T>
+  static MS_DEV void vjp(const T* th, const T (&x)[NX], T dt, const T (&GA)[NX][NX],
+                         const T (&Gb)[NX], const T (&GC)[NX][NX], const T (&GR)[NY][NY],
+                         double (&out)[NTH]) {
+    (void)th;
+    const double x1 = x[0], x2 = x[1], h = dt;
+    // dF/dmu = [[0, 0], [-2 x1 x2, 1 - x1^2]]; dA = -dt dF
+    // dc/dmu = df/dmu - dF/dmu x = (0, 2 x1^2 x2); db = -dt dc
+    out[0] += -h * (double(GA[1][0]) * (-2.0 * x1 * x2) + double(GA[1][1]) * (1.0 - x1 * x1))
+              - h * double(Gb[1]) * (2.0 * x1 * x1 * x2);
+    out[1] += h * (double(GC[0][0]) + double(GC[1][1]));
+    out[2] += double(GR[0][0]);
+  }
+};
+
+// ------------------------------------------------------------------ Lorenz-63
+// theta = (sigma, rho, beta, q, r): f = (sigma (x2 - x1), x1 (rho - x3) - x2,
+// x1 x2 - beta x3), L = I, W = q I, h = x, R = r I.
+struct ModelLorenz63 {
+  static constexpr int NX = 3, NY = 3, NW = 3, NTH = 5;
+  static constexpr bool kNonlinear = true;
+  static constexpr bool kAdjoint = true;
+
+  template <typename T>
+  static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {
+    const T sg = th[0], rho = th[1], be = th[2], q = th[3], rr = th[4];
+    const T x1 = x[0], x2 = x[1], x3 = x[2];
+    s.dt = dt;
+    s.F[0][0] = -sg; s.F[0][1] = sg;   s.F[0][2] = T(0);
+    s.F[1][0] = rho - x3; s.F[1][1] = T(-1); s.F[1][2] = -x1;
+    s.F[2][0] = x2;  s.F[2][1] = x1;   s.F[2][2] = -be;
+    // c = f(x) - F x: only the bilinear terms survive
+    s.c[0] = T(0);
+    s.c[1] = x1 * x3;   // x1 (rho - x3) - x2 - [(rho - x3) x1 - x2 - x1 x3]
+    s.c[2] = -x1 * x2;  // x1 x2 - be x3 - [x2 x1 + x1 x2 - be x3]
+    const T sv = sqrt_(dt * q);
+    const T ri = rcp(rr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        s.V[i][j] = i == j ? sv : T(0);
+        s.H[i][j] = i == j ? T(1) : T(0);
+        s.R[i][j] = i == j ? rr : T(0);
+        s.Rinv[i][j] = i == j ? ri : T(0);
+      }
+      s.r[i] = T(0);
+    }
+  }
+
+  template <typename T>
+  static MS_DEV void vjp(const T* th, const T (&x)[NX], T dt, const T (&GA)[NX][NX],
+                         const T (&)[NX], const T (&GC)[NX][NX], const T (&GR)[NY][NY],
+                         double (&out)[NTH]) {
+    (void)th;
+    (void)x;
+    const double h = dt;
+    // dA = -dt dF; dF/dsigma = [[-1, 1, 0], 0, 0], dF/drho = e_1 e_0^T, dF/dbeta = -e_2 e_2^T.
+    // c carries no theta dependence (f is linear in theta along the linear terms).
+    out[0] += -h * (-double(GA[0][0]) + double(GA[0][1]));
+    out[1] += -h * double(GA[1][0]);
+    out[2] += h * double(GA[2][2]);
+    out[3] += h * (double(GC[0][0]) + double(GC[1][1]) + double(GC[2][2]));
+    out[4] += double(GR[0][0]) + double(GR[1][1]) + double(GR[2][2]);
+  }
+};
+
+// ------------------------------------------------------------------ general linear
+// Dense F, c, L, W, H, r, R read per step (or shared when the stride is 0).
+// Forward path only (no parameter adjoint).
+template <int NX_, int NY_, int NW_>
+struct ModelLinear {
+  static constexpr int NX = NX_, NY = NY_, NW = NW_, NTH = 0;
+  static constexpr bool kNonlinear = false;
+  static constexpr bool kAdjoint = false;
+};
+
+}  // namespace ms

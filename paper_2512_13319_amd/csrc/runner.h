@@ -1,0 +1,70 @@
+// Launch sequences behind the C-ABI, one instantiation per (dtype, model).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mapscan.h"
+
+namespace ms {
+
+constexpr int kChunk = 16;  // states per lane
+
+struct WsLayout {
+  int64_t n_lanes;   // padded to whole tiles
+  int64_t n_tiles;
+  size_t off[7];     // counters, lane_pre, tile_agg, tile_carry, slane_pre, stile_agg, stile_carry
+  size_t total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz) {
+  WsLayout w;
+  const int64_t nl = (n_states + kChunk - 1) / kChunk;
+  w.n_tiles = (nl + 63) / 64;
+  w.n_lanes = w.n_tiles * 64;
+  const int64_t sym = nx * (nx + 1) / 2;
+  const int64_t elem = nx * nx + 2 * nx + 2 * sym;
+  const int64_t aff = nx * nx + nx + sym;
+  const size_t sizes[7] = {256,
+                           size_t(elem * w.n_lanes) * sz,
+                           size_t(elem * w.n_tiles) * sz,
+                           size_t((sym + nx) * w.n_tiles) * sz,
+                           size_t(aff * w.n_lanes) * sz,
+                           size_t(aff * w.n_tiles) * sz,
+                           size_t((nx + sym) * w.n_tiles) * sz};
+  size_t o = 0;
+  for (int i = 0; i < 7; ++i) {
+    w.off[i] = o;
+    o += align256(sizes[i]);
+  }
+  w.total = o;
+  return w;
+}
+
+struct SmoothArgs {
+  void* S;
+  void* v;
+  void* m;
+  void* P;
+  void* xs;
+  void* Ps;
+  double* loglik;
+  double* obj;
+  double* g_loglik;
+  double* g_obj;
+  void* ws;
+  hipStream_t stream;
+};
+
+template <typename T, class M>
+struct Runner {
+  static hipError_t build(const map_problem& p, void* elems, hipStream_t st);
+  static hipError_t filter(const map_problem& p, const SmoothArgs& a);
+  static hipError_t smoother(const map_problem& p, const SmoothArgs& a, bool grad);
+  static hipError_t smooth(const map_problem& p, const SmoothArgs& a);
+  static hipError_t init_xbar(const map_problem& p, void* xbar, hipStream_t st);
+};
+
+}  // namespace ms

@@ -1,0 +1,180 @@
+// Definitions of the launch sequences (included by the instantiation units).
+#pragma once
+#include "kernels.h"
+#include "runner.h"
+
+namespace ms {
+
+template <typename T>
+inline Prob<T> make_prob(const map_problem& q) {
+  Prob<T> p;
+  p.n_seg = q.n_seg;
+  p.n_steps = q.n_steps;
+  p.n_states = q.n_steps + q.n_seg;
+  p.seg_off = q.seg_off;
+  p.dt = static_cast<const T*>(q.dt);
+  p.dt_stride = q.dt_stride;
+  p.y = static_cast<const T*>(q.y);
+  p.m0 = static_cast<const T*>(q.m0);
+  p.m0_stride = q.m0_stride;
+  p.P0 = static_cast<const T*>(q.P0);
+  p.P0_stride = q.P0_stride;
+  p.theta = static_cast<const T*>(q.theta);
+  p.th_stride = q.theta_stride;
+  p.xbar = static_cast<const T*>(q.xbar);
+  p.F = static_cast<const T*>(q.F);
+  p.c = static_cast<const T*>(q.c);
+  p.L = static_cast<const T*>(q.L);
+  p.W = static_cast<const T*>(q.W);
+  p.H = static_cast<const T*>(q.H);
+  p.r = static_cast<const T*>(q.r);
+  p.R = static_cast<const T*>(q.R);
+  p.sF = q.F_stride;
+  p.sc = q.c_stride;
+  p.sL = q.L_stride;
+  p.sW = q.W_stride;
+  p.sH = q.H_stride;
+  p.sr = q.r_stride;
+  p.sR = q.R_stride;
+  return p;
+}
+
+template <typename T>
+inline Ws<T> make_ws(int nx, int64_t n_states, void* base) {
+  WsLayout l = ws_layout(nx, n_states, sizeof(T));
+  char* b = static_cast<char*>(base);
+  Ws<T> w;
+  w.counters = reinterpret_cast<unsigned int*>(b + l.off[0]);
+  w.lane_pre = reinterpret_cast<T*>(b + l.off[1]);
+  w.tile_agg = reinterpret_cast<T*>(b + l.off[2]);
+  w.tile_carry = reinterpret_cast<T*>(b + l.off[3]);
+  w.slane_pre = reinterpret_cast<T*>(b + l.off[4]);
+  w.stile_agg = reinterpret_cast<T*>(b + l.off[5]);
+  w.stile_carry = reinterpret_cast<T*>(b + l.off[6]);
+  w.n_lanes = l.n_lanes;
+  w.n_tiles = l.n_tiles;
+  return w;
+}
+
+inline unsigned grid_for(int64_t n_tiles) { return unsigned((n_tiles + 3) / 4); }
+
+inline hipError_t zero(double* a, int64_t n, hipStream_t st) {
+  if (a == nullptr || n <= 0) return hipSuccess;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  const unsigned g = unsigned(nb < 1024 ? nb : 1024);
+  k_zero<<<g, kBlock, 0, st>>>(a, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_init_xbar(Prob<T> p, int nx, T* xb) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= p.n_states) return;
+  int64_t lo = 0, hi = p.n_seg - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (p.seg_off[mid] + mid <= i) lo = mid; else hi = mid - 1;
+  }
+  for (int c = 0; c < nx; ++c) xb[c * p.n_states + i] = p.m0[lo * p.m0_stride + c];
+}
+
+#define MS_CHECK(x)                         \
+  do {                                      \
+    hipError_t e_ = (x);                    \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+
+template <typename T, class M>
+hipError_t Runner<T, M>::build(const map_problem& q, void* elems, hipStream_t st) {
+  Prob<T> p = make_prob<T>(q);
+  const unsigned g = unsigned((p.n_states + kBlock - 1) / kBlock);
+  k_build_elements<T, M><<<g, kBlock, 0, st>>>(p, static_cast<T*>(elems));
+  return hipGetLastError();
+}
+
+template <typename T, class M>
+hipError_t Runner<T, M>::init_xbar(const map_problem& q, void* xbar, hipStream_t st) {
+  Prob<T> p = make_prob<T>(q);
+  const unsigned g = unsigned((p.n_states + kBlock - 1) / kBlock);
+  k_init_xbar<T><<<g, kBlock, 0, st>>>(p, M::NX, static_cast<T*>(xbar));
+  return hipGetLastError();
+}
+
+template <typename T, class M>
+hipError_t Runner<T, M>::filter(const map_problem& q, const SmoothArgs& a) {
+  Prob<T> p = make_prob<T>(q);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  MS_CHECK(zero(a.loglik, q.n_seg, a.stream));
+  const unsigned g = grid_for(w.n_tiles);
+  k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  MS_CHECK(hipGetLastError());
+  FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
+  Acc acc{a.loglik, nullptr, nullptr, nullptr};
+  k_filter_down<T, M, kChunk, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  return hipGetLastError();
+}
+
+template <typename T, class M>
+hipError_t Runner<T, M>::smoother(const map_problem& q, const SmoothArgs& a, bool grad) {
+  Prob<T> p = make_prob<T>(q);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  const int64_t nth = M::NTH;
+  MS_CHECK(zero(a.obj, q.n_seg, a.stream));
+  if (grad) {
+    MS_CHECK(zero(a.g_loglik, q.n_seg * nth, a.stream));
+    MS_CHECK(zero(a.g_obj, q.n_seg * nth, a.stream));
+  }
+  const unsigned g = grid_for(w.n_tiles);
+  FilterOut fo{a.S, a.v, nullptr, nullptr, 0};
+  Acc acc{nullptr, a.obj, a.g_loglik, a.g_obj};
+  k_filter_down<T, M, kChunk, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  MS_CHECK(hipGetLastError());
+  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
+  if constexpr (M::kAdjoint) {
+    if (grad) {
+      k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      return hipGetLastError();
+    }
+  }
+  to.want_grad = 0;
+  k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  return hipGetLastError();
+}
+
+template <typename T, class M>
+hipError_t Runner<T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
+  Prob<T> p = make_prob<T>(q);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  const int64_t nth = M::NTH;
+  const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
+  MS_CHECK(zero(a.loglik, q.n_seg, a.stream));
+  MS_CHECK(zero(a.obj, q.n_seg, a.stream));
+  if (grad) {
+    MS_CHECK(zero(a.g_loglik, q.n_seg * nth, a.stream));
+    MS_CHECK(zero(a.g_obj, q.n_seg * nth, a.stream));
+  }
+  const unsigned g = grid_for(w.n_tiles);
+  k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  MS_CHECK(hipGetLastError());
+  FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
+  Acc acc{a.loglik, a.obj, a.g_loglik, a.g_obj};
+  k_filter_down<T, M, kChunk, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  MS_CHECK(hipGetLastError());
+  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
+  if constexpr (M::kAdjoint) {
+    if (grad) {
+      k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      return hipGetLastError();
+    }
+  }
+  to.want_grad = 0;
+  k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  return hipGetLastError();
+}
+
+#define MS_COMMA ,
+#define MS_INSTANTIATE(M)                 \
+  template struct Runner<float, M>;       \
+  template struct Runner<double, M>;
+
+}  // namespace ms

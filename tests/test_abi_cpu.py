@@ -1,0 +1,177 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/mapscan.h declares, and rejects bad arguments on the host before
+launching anything.  Every call below is built to fail validation, so no
+kernel is ever launched (device pointers are dummies)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_13319_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mapscan.h")
+
+FAKE = 0x1000  # never dereferenced: validation fails first
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(map_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_lib.EXPORTS)
+    v = int(re.search(r"#define MAPSCAN_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert lib.map_abi_version() == v
+
+
+def test_struct_layout_matches_header():
+    """The ctypes mirror lists the struct fields in header order."""
+    txt = open(HEADER).read()
+    body = txt[txt.index("typedef struct {"):txt.index("} map_problem;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"([A-Za-z_0-9]+)\s*[,;]", body)
+    assert fields == [f for f, _ in _lib.MapProblem._fields_]
+
+
+def good(seg_host):
+    p = _lib.MapProblem()
+    p.nx, p.ny, p.nw = 4, 2, 2
+    p.dtype = _lib.MAP_F64
+    p.model = _lib.MODELS["cv"]
+    p.n_theta = 3
+    p.n_seg = len(seg_host) - 1
+    p.n_steps = int(seg_host[-1])
+    p.seg_off = FAKE
+    p.seg_off_host = seg_host.ctypes.data
+    p.dt = FAKE
+    p.dt_stride = 1
+    p.y = FAKE
+    p.m0, p.P0, p.theta = FAKE, FAKE, FAKE
+    p.m0_stride, p.P0_stride, p.theta_stride = 4, 16, 3
+    return p
+
+
+def status_of(fn, *args):
+    return fn(*args)
+
+
+@pytest.fixture
+def seg():
+    return np.array([0, 100, 250], dtype=np.int64)
+
+
+def test_workspace_bytes(seg):
+    lib = _lib.load()
+    p = good(seg)
+    n = lib.map_workspace_bytes(ctypes.byref(p))
+    assert n > 0
+    p2 = good(seg)
+    p2.dtype = _lib.MAP_F32
+    assert 0 < lib.map_workspace_bytes(ctypes.byref(p2)) < n
+    p2.nx = 9
+    assert lib.map_workspace_bytes(ctypes.byref(p2)) == 0
+    assert b"outside" in lib.map_last_error()
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda p: setattr(p, "dtype", 7), -3),
+    (lambda p: setattr(p, "nx", 0), -2),
+    (lambda p: setattr(p, "ny", 9), -2),
+    (lambda p: setattr(p, "model", 17), -1),
+    (lambda p: setattr(p, "n_theta", 2), -2),
+    (lambda p: setattr(p, "n_seg", 0), -2),
+    (lambda p: setattr(p, "seg_off", None), -1),
+    (lambda p: setattr(p, "dt", None), -1),
+    (lambda p: setattr(p, "dt_stride", 3), -1),
+    (lambda p: setattr(p, "y", None), -1),
+    (lambda p: setattr(p, "P0", None), -1),
+    (lambda p: setattr(p, "theta", None), -1),
+    (lambda p: setattr(p, "m0_stride", -4), -1),
+    (lambda p: (setattr(p, "nx", 5), setattr(p, "ny", 2), setattr(p, "nw", 2)), -8),
+])
+def test_filter_rejects_bad_problem(seg, mutate, expect):
+    lib = _lib.load()
+    p = good(seg)
+    mutate(p)
+    st = lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40, None)
+    assert st == expect, (st, lib.map_last_error())
+    assert lib.map_last_error()
+
+
+def test_layout_errors():
+    lib = _lib.load()
+    bad = np.array([0, 100, 50], dtype=np.int64)
+    p = good(bad)
+    p.n_steps = 50
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, FAKE,
+                          1 << 40, None) == -4
+    bad2 = np.array([1, 100, 250], dtype=np.int64)
+    assert lib.map_smooth(ctypes.byref(good(bad2)), FAKE, FAKE, FAKE, None, None, None, None,
+                          None, FAKE, 1 << 40, None) == -4
+    seg = np.array([0, 100, 250], dtype=np.int64)
+    p3 = good(seg)
+    p3.n_steps = 251
+    assert lib.map_smooth(ctypes.byref(p3), FAKE, FAKE, FAKE, None, None, None, None, None, FAKE,
+                          1 << 40, None) == -4
+
+
+def test_workspace_and_output_checks(seg):
+    lib = _lib.load()
+    p = good(seg)
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 16, None) == -7
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, None, 1 << 40,
+                               None) == -7
+    assert lib.map_filter_scan(ctypes.byref(p), None, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, 1 << 40,
+                               None) == -1
+    assert lib.map_smoother_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                                 None) == -1
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE,
+                            1 << 40, None) == -1
+    assert lib.map_iterated_nonlinear(ctypes.byref(p), 0, None, FAKE, FAKE, FAKE, FAKE, None, None,
+                                      None, None, None, FAKE, 1 << 40, None) == -1
+    assert lib.map_iterated_nonlinear(ctypes.byref(p), 2, None, FAKE, FAKE, FAKE, FAKE, None, None,
+                                      None, None, None, FAKE, 1 << 40, None) == -1  # aliasing
+    assert lib.map_build_elements(ctypes.byref(p), None, None) == -1
+    assert lib.map_filter_scan(None, FAKE, FAKE, None, None, None, FAKE, 1 << 40, None) == -1
+
+
+def test_gradients_need_parametric_model():
+    lib = _lib.load()
+    seg = np.array([0, 100], dtype=np.int64)
+    p = good(seg)
+    p.model = _lib.MODELS["linear"]
+    p.n_theta = 0
+    p.nx, p.ny, p.nw = 2, 1, 1
+    for k in ("F", "c", "L", "W", "H", "r", "R"):
+        setattr(p, k, FAKE)
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE, FAKE,
+                          1 << 40, None) == -8
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, FAKE, FAKE,
+                            1 << 40, None) == -8
+    p.R = None
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+
+
+def test_nonlinear_model_needs_xbar():
+    lib = _lib.load()
+    seg = np.array([0, 100], dtype=np.int64)
+    p = good(seg)
+    p.model = _lib.MODELS["vdp"]
+    p.nx, p.ny, p.nw = 2, 1, 2
+    p.m0_stride, p.P0_stride = 2, 4
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+    assert b"xbar" in lib.map_last_error()

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Metric (componentwise normalised): for every output component c,
+rel_c = max_k |gpu - ref| / max_k |ref|; the case passes when max_c rel_c is
+at most 1e-9 in FP64 and 1e-4 in FP32 (the FP32 run and the FP64 oracle see
+the same FP32-rounded inputs).  Per-segment scalars (log-likelihood,
+objective) are compared relative to their magnitude; gradients at 1e-6 (FP64).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import cref, ref
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-9, "f32": 1e-4}
+TORCH_DT = {"f64": torch.float64, "f32": torch.float32}
+
+
+def _mapscan():
+    import paper_2512_13319_amd as ms
+    return ms
+
+
+def rel_err(gpu, refv):
+    """max over components of max_k |gpu - ref| / max_k |ref|; arrays [n, comps...]."""
+    g = np.asarray(gpu, dtype=np.float64).reshape(gpu.shape[0], -1)
+    r = np.asarray(refv, dtype=np.float64).reshape(refv.shape[0], -1)
+    num = np.abs(g - r).max(0)
+    den = np.maximum(np.abs(r).max(0), 1e-300)
+    return float((num / den).max())
+
+
+def sym_full(ms, planes, nx):
+    return ms.sym_to_full(planes, nx).double().cpu().numpy()
+
+
+def planes_T(t):
+    return t.double().cpu().numpy().T
+
+
+def _oracle(wl):
+    if wl.model in ("vdp", "lorenz63"):
+        return cref.iterate(wl)
+    return cref.smooth(wl)
+
+
+CASES = {
+    "cfg1_wiener": lambda: workloads.config(1),
+    "cv2d_ragged": lambda: workloads.cv(T=3 * 4096 + 123, d=2, dt=1e-3, q=0.5, r=0.05,
+                                        m0=[5, 5, 0, 0], P0=1e-2 * np.eye(4), seed=12, gamma=0.2),
+    "cv_batched": lambda: workloads.cv_batched(n_seg=37, lmin=2.0, lmax=9.0, seed=13),
+    "linear_tv": lambda: workloads.linear_random(T=700, nx=3, ny=2, nw=3, seed=14, n_seg=3),
+    "linear_singular": lambda: workloads.linear_random(T=900, nx=4, ny=2, nw=2, seed=15),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_linear_smoother_parity(case, dtype):
+    ms = _mapscan()
+    wl = CASES[case]().rounded(dtype)
+    o = _oracle(wl)
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
+    r = ms.smooth(p, covariances=True, loglik=True, objective=True)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    nx = wl.nx
+    e_xs = rel_err(planes_T(r["xs"]), o["xs"])
+    e_Ps = rel_err(sym_full(ms, r["Ps"], nx), o["Ps"])
+    S = sym_full(ms, r["S"], nx)
+    v = planes_T(r["v"])
+    Sref = np.linalg.inv(o["P"])
+    vref = np.einsum("kij,kj->ki", Sref, o["m"])
+    e_S = rel_err(S, Sref)
+    e_v = rel_err(v, vref)
+    ll = r["loglik"].cpu().numpy()
+    ob = r["obj"].cpu().numpy()
+    e_ll = np.abs(ll - o["loglik"]).max() / np.abs(o["loglik"]).max()
+    e_ob = np.abs(ob - o["mstar"]).max() / np.abs(o["mstar"]).max()
+    msg = f"{case} {dtype}: xs {e_xs:.2e} Ps {e_Ps:.2e} S {e_S:.2e} v {e_v:.2e} ll {e_ll:.2e} obj {e_ob:.2e}"
+    print(msg)
+    for e in (e_xs, e_Ps, e_S, e_v):
+        assert e <= tol, msg
+    assert e_ll <= tol and e_ob <= tol, msg
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_filter_moments_and_separate_smoother(dtype):
+    """map_filter_scan (with m, P) followed by map_smoother_scan equals the
+    fused map_smooth and the oracle."""
+    ms = _mapscan()
+    wl = CASES["cv_batched"]().rounded(dtype)
+    o = cref.smooth(wl)
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
+    f = ms.filter_scan(p, moments=True, loglik=True)
+    s = ms.smoother_scan(p, f["S"], f["v"], covariances=True, objective=True)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    assert rel_err(planes_T(f["m"]), o["m"]) <= tol
+    assert rel_err(sym_full(ms, f["P"], wl.nx), o["P"]) <= tol
+    assert rel_err(planes_T(s["xs"]), o["xs"]) <= tol
+    assert rel_err(sym_full(ms, s["Ps"], wl.nx), o["Ps"]) <= tol
+    assert np.abs(f["loglik"].cpu().numpy() - o["loglik"]).max() <= tol * np.abs(o["loglik"]).max()
+    assert np.abs(s["obj"].cpu().numpy() - o["mstar"]).max() <= tol * np.abs(o["mstar"]).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["vdp", "lorenz63"])
+def test_nonlinear_iterates_parity(model, dtype):
+    """Each Gauss-Newton iterate is the exact solution of a linear problem;
+    compare the final iterate and the last solve's outputs."""
+    ms = _mapscan()
+    if model == "vdp":
+        wl = workloads.vdp(T=5000, seed=31, n_iter=4)
+    else:
+        wl = workloads.lorenz63(n_seg=5, T=600, seed=32, n_iter=3)
+    wl = wl.rounded(dtype)
+    o = cref.iterate(wl)
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
+    r = ms.iterated_nonlinear(p, wl.n_iter, covariances=True, loglik=True, objective=True)
+    torch.cuda.synchronize()
+    tol = TOL[dtype] * (10 if dtype == "f32" else 1)
+    e_xs = rel_err(planes_T(r["xs"]), o["xs"])
+    e_xb = rel_err(planes_T(r["xbar"]), o["xbar"].T)
+    e_Ps = rel_err(sym_full(ms, r["Ps"], wl.nx), o["Ps"])
+    msg = f"{model} {dtype}: xs {e_xs:.2e} xbar {e_xb:.2e} Ps {e_Ps:.2e}"
+    print(msg)
+    assert e_xs <= tol and e_xb <= tol and e_Ps <= tol, msg
+
+
+@pytest.mark.parametrize("model", ["cv", "vdp", "lorenz63"])
+def test_gradients_match_oracle_autograd(model):
+    """Fused adjoint (Fisher identity for the log-likelihood, envelope theorem
+    for the objective) against autograd of the sequential oracle, FP64."""
+    ms = _mapscan()
+    if model == "cv":
+        wl = workloads.cv(T=300, d=2, dt=0.01, gamma=0.3, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                          P0=1e-2 * np.eye(4), seed=41)
+        xbar = None
+    elif model == "vdp":
+        wl = workloads.vdp(T=300, dt=0.01, seed=42, n_iter=3)
+    else:
+        wl = workloads.lorenz63(n_seg=2, T=200, dt=0.005, seed=43, n_iter=2)
+    p = ms.problem_from_workload(wl, dtype=torch.float64)
+    if model == "cv":
+        r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
+    else:
+        r = ms.iterated_nonlinear(p, wl.n_iter, grad=True)
+    torch.cuda.synchronize()
+    gl_gpu = r["g_loglik"].cpu().numpy()
+    gm_gpu = r["g_obj"].cpu().numpy()
+    o = cref.iterate(wl) if model != "cv" else None
+    for s in range(wl.n_seg):
+        seg = ref.workload_segment(wl, s)
+        st = wl.seg_states(s)
+        T = wl.seg_off[s + 1] - wl.seg_off[s]
+        xb = torch.zeros(T + 1, wl.nx, dtype=torch.float64) if o is None else \
+            torch.tensor(o["xbar"][:, st].T.copy())
+        gl, gm, _ = ref.gradients(wl.model, wl.nx, seg, xb)
+        gl, gm = gl.numpy(), gm.numpy()
+        el = np.abs(gl_gpu[s] - gl).max() / max(1.0, np.abs(gl).max())
+        em = np.abs(gm_gpu[s] - gm).max() / max(1.0, np.abs(gm).max())
+        print(model, s, gl_gpu[s], gl, gm_gpu[s], gm)
+        assert el <= 1e-6 and em <= 1e-6, (model, s, gl_gpu[s], gl, gm_gpu[s], gm)
