@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Throughput of the parallel-in-time MAP smoother on one MI355X.
+
+One step = one pass of the whole hot path over the workload resident in HBM:
+filter scan (information form), trajectory scan with smoothed covariances,
+log-likelihood and objective, and the fused adjoint (gradients of both with
+respect to the constant-velocity parameters gamma, q, r).  The default
+workload is the 2-D constant-velocity tracking SDE with nx = 4, ny = 2,
+T = 2^20 uniform steps (dt = 1e-3), one trajectory.
+
+Prints one JSON line.  Kernel durations for the roofline come from HIP events
+the library records around each launch on its stream during the timed loop.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "smoothed time-steps/sec (fwd+adjoint) at nx=4, T=2^20, vs plain scan; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}  # packed FP32 is not generated
+
+
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def kernel_bytes(nx, ny, s, kind):
+    """Algorithmic HBM bytes per state of each pass (each input read once,
+    each output written once; the pass-to-pass intermediate S, v counted once
+    as written by the filter and once as read by the trajectory pass)."""
+    sym = nx * (nx + 1) // 2
+    return {
+        "filter_up": ny * s,                              # read y
+        "fused_down": (ny + sym + nx) * s,                # read y, write S, v
+        "traj_down": (sym + nx + ny + nx + sym) * s,      # read S, v, y; write xs, Ps
+        "traj_down_adjoint": (sym + nx + ny + nx + sym) * s,
+    }[kind]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--log2T", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=6144)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures a single GPU: this build runs the scan on one MI355X "
+              "(multi-GPU sharding is a design note only); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_13319_amd as ms
+    import workloads
+    from paper_2512_13319_amd import _lib
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    T = 2 ** args.log2T
+    wl = workloads.cv(T=T, d=2, dt=1e-3, q=0.5, r=0.05, m0=[5, 5, 0, 0], P0=1e-2 * np.eye(4),
+                      seed=2, name="cfg2_cv2d")
+    p = ms.problem_from_workload(wl, dtype=tdt, device=dev)
+    nsym = p.nsym
+    out = dict(S=p._tiled(nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx), Ps=p._tiled(nsym),
+               loglik=p._empty(1, dtype=torch.float64), obj=p._empty(1, dtype=torch.float64),
+               g_loglik=p._empty(1, 3, dtype=torch.float64), g_obj=p._empty(1, 3, dtype=torch.float64))
+    lib = _lib.load()
+
+    def step_fwdadj():
+        ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True, out=out,
+                  natural=False)
+
+    def step_plain():
+        ms.smooth(p, covariances=True, loglik=False, objective=False, grad=False, out=out,
+                  natural=False)
+
+    def timed(fn, steps, warmup, profile):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        if profile:
+            _lib.check(lib.map_profile_enable(steps * 8))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_step = e0.elapsed_time(e1) / steps
+        kern = {}
+        if profile:
+            import ctypes
+            for name, kind in _lib.PROF_KINDS.items():
+                c = ctypes.c_int64()
+                tot = ctypes.c_double()
+                _lib.check(lib.map_profile_read(kind, ctypes.byref(c), ctypes.byref(tot)))
+                if c.value:
+                    kern[name] = (c.value, tot.value / c.value)
+            _lib.check(lib.map_profile_enable(0))
+        return ms_step, wall / steps * 1e3, kern
+
+    ms_fa, wall_fa, kern_fa = timed(step_fwdadj, args.steps, args.warmup, True)
+    ms_pl, wall_pl, kern_pl = timed(step_plain, args.steps, args.warmup, True)
+
+    s = 8 if args.dtype == "f64" else 4
+    # dominant kernel of the fwd+adjoint step
+    dom = max((k for k in kern_fa if k != "aux"), key=lambda k: kern_fa[k][1])
+    dom_ms = kern_fa[dom][1]
+    bytes_dom = kernel_bytes(p.nx, p.ny, s, dom) * p.n_states
+    achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
+    step_bytes = (p.ny + 2 * (nsym + p.nx) + p.nx + nsym) * s * p.n_states
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "kernel_ms": round(dom_ms, 4),
+                "kernels_ms": {k: round(v[1], 4) for k, v in kern_fa.items()},
+                "step_hbm_frac": round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    res = {
+        "metric": METRIC,
+        "value": T / (ms_fa * 1e-3),
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_fa,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "2-D constant-velocity SDE nx=4 ny=2, T=2^%d steps dt=1e-3, q=0.5, "
+                               "r=0.05, one trajectory; filter + smoother (x*, P^s) + log-lik + "
+                               "objective + adjoint d/d(gamma,q,r)" % args.log2T,
+                   "T": T, "nx": 4, "ny": 2, "n_seg": 1},
+        "plain_scan": {"value": T / (ms_pl * 1e-3), "ms_per_step": ms_pl,
+                       "kernels_ms": {k: round(v[1], 4) for k, v in kern_pl.items()}},
+        "wall_ms_per_step": round(wall_fa, 4),
+        "roofline": roofline,
+    }
+
+    if args.copy_calibration:
+        # plain device-to-device copy of a known size, read and written once
+        nbytes = 256 << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = nbytes
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+    print(json.dumps(res))
+
+
+def cpu_baseline(wl, n):
+    """The sequential oracle (PyTorch FP64 per-step loop, gradients by autograd)
+    on the first n steps of the same trajectory, one thread."""
+    import torch
+
+    from oracle import ref
+    import workloads
+
+    torch.set_num_threads(1)
+    sub = workloads.Workload(**{**wl.__dict__})
+    sub.seg_off = wl.seg_off.copy()
+    sub.seg_off[-1] = n
+    sub.dt = wl.dt[:n]
+    sub.y = wl.y[:, :n]
+    seg = ref.workload_segment(sub, 0)
+    t0 = time.perf_counter()
+    ref.gradients("cv", 4, seg, torch.zeros(n + 1, 4, dtype=torch.float64))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the same trajectory: sequential Kalman filter + RTS "
+                      "smoother + log-likelihood + objective, gradients by autograd, FP64, "
+                      "%.1f s" % (n, dt),
+            "cpu": cpu_info()}
+
+
+if __name__ == "__main__":
+    main()

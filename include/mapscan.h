@@ -33,11 +33,19 @@
  *  - Steps of all segments are concatenated: segment s owns steps
  *    seg_off[s] .. seg_off[s+1]-1 and states seg_off[s]+s .. seg_off[s+1]+s
  *    (T_s steps give T_s+1 states; state seg_off[s]+s is the prior time t0).
- *    n_states = n_steps + n_seg.
- *  - Layout is structure-of-arrays: component c of item i is at
- *    base[c * n + i] with n = n_steps for step-indexed arrays and n = n_states
- *    for state-indexed arrays.  Symmetric nx x nx matrices are stored as
- *    nx(nx+1)/2 planes, lower triangle in row order (0,0),(1,0),(1,1),(2,0)...
+ *    n_states = n_steps + n_seg.  Step k of segment s ends at state k + s + 1.
+ *  - State-indexed arrays use the TILED layout (MAPSCAN_TILE = 1024 states
+ *    per tile, matching the kernels' work unit of 64 lanes x 16 consecutive
+ *    states).  For an array with C components, component c of state i is at
+ *        ((i / 1024) * C + c) * 1024 + (i % 16) * 64 + (i / 16) % 64,
+ *    and the buffer holds ceil(n_states / 1024) * C * 1024 elements (the
+ *    caller allocates the padding; padded entries are never read as data and
+ *    may be written).  This makes every access of a wavefront a contiguous
+ *    run.  Measurements y and per-step lengths dt are given per state too:
+ *    the value of the step that ends at state i (entries at a segment's first
+ *    state are ignored).
+ *  - Symmetric nx x nx matrices are nx(nx+1)/2 components, lower triangle in
+ *    row order (0,0),(1,0),(1,1),(2,0)...
  *  - Errors: every entry returns a map_status; arguments are validated on the
  *    host before anything is launched, and a failing check launches nothing.
  *    map_last_error() gives a readable message for the calling thread.
@@ -54,7 +62,8 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 1
+#define MAPSCAN_ABI_VERSION 2
+#define MAPSCAN_TILE 1024
 
 typedef enum {
   MAP_OK = 0,
@@ -96,16 +105,16 @@ typedef struct {
   int64_t n_steps;         /* total steps = seg_off[n_seg] */
   const int64_t* seg_off;       /* device [n_seg+1]: 0 = seg_off[0] <= seg_off[1] <= ... */
   const int64_t* seg_off_host;  /* optional host copy; when given it is validated */
-  const void* dt;          /* device: dt_k at dt[k * dt_stride], > 0 */
-  int64_t dt_stride;       /* 1 (per step) or 0 (one shared value) */
-  const void* y;           /* device [ny][n_steps]: y_k measures the state x_k */
+  const void* dt;          /* device: one value (dt_stride 0) or tiled [1] per state, > 0 */
+  int64_t dt_stride;       /* 0 (one shared value) or 1 (tiled per state) */
+  const void* y;           /* device, tiled [ny] per state: measurement of that state */
   const void* m0;          /* device [n_seg][nx] prior means (m0_stride = nx, or 0: shared) */
   int64_t m0_stride;
   const void* P0;          /* device [n_seg][nx*nx] row-major SPD prior covariances */
   int64_t P0_stride;       /* nx*nx, or 0: shared */
   const void* theta;       /* device [n_seg][n_theta] (theta_stride = n_theta, or 0: shared) */
   int64_t theta_stride;
-  const void* xbar;        /* device [nx][n_states] linearisation states (nonlinear models) */
+  const void* xbar;        /* device, tiled [nx] per state: linearisation states (nonlinear) */
   /* MAP_MODEL_LINEAR only: row-major per-step matrices F [nx*nx], c [nx],
    * L [nx*nw], W [nw*nw] (SPD), H [ny*nx], r [ny], R [ny*ny] (SPD); matrix of
    * step k at base + k * stride (stride 0: one matrix for all steps). */
@@ -127,13 +136,13 @@ map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream);
  * prior element (A = 0, b = 0, C = 0, eta = P0^{-1} m0, J = P0^{-1}) at a
  * segment's first state -- as planes
  *   A (nx*nx, row-major), b (nx), C (sym), eta (nx), J (sym)
- * i.e. [nx*nx + 2 nx + nx(nx+1)][n_states] in `elems`. */
+ * i.e. nx*nx + 2 nx + nx(nx+1) tiled components per state in `elems`. */
 map_status map_build_elements(const map_problem* p, void* elems, void* stream);
 
 /* Filter scan (Sec. 3.4 eq. valueparallel with the combination rule of
  * Sec. 4.1; information form of the Kalman--Bucy filter, Sec. 2.5):
- *   S     out [nx(nx+1)/2][n_states]  information matrix S_k = P_k^{-1}
- *   v     out [nx][n_states]          information vector v_k = P_k^{-1} m_k
+ *   S     out tiled [nx(nx+1)/2] per state: information matrix S_k = P_k^{-1}
+ *   v     out tiled [nx] per state:         information vector v_k = P_k^{-1} m_k
  *   m, P  optional out (NULL to skip) filter mean and covariance
  *   loglik optional out [n_seg] (double): log p(y_1..y_T) by the
  *         prediction-error decomposition of the same discrete model. */
@@ -142,8 +151,8 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
 
 /* Trajectory scan (Sec. 4.3, eq. 42: x*_{k-1} = G_k x*_k + beta_k composed by an
  * associative affine scan in reverse time order) from the filter's S, v:
- *   xs    out [nx][n_states] MAP trajectory = smoothed means
- *   Ps    optional out [nx(nx+1)/2][n_states] smoothed covariances
+ *   xs    out tiled [nx] per state: MAP trajectory = smoothed means
+ *   Ps    optional out tiled [nx(nx+1)/2] per state: smoothed covariances
  *   obj   optional out [n_seg] (double): the discretised OM objective (without
  *         the divergence term) at xs. */
 map_status map_smoother_scan(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
@@ -160,7 +169,7 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
 
 /* Iterated Taylor linearisation (Sec. 4.4): xbar^(0) = xbar0 (NULL: m0 of each
  * segment at every state), then n_iter times: linearise about xbar, solve
- * with map_smooth, xbar <- xs.  xbar_buf [nx][n_states] is caller scratch that
+ * with map_smooth, xbar <- xs.  xbar_buf (tiled [nx] per state) is caller scratch that
  * holds the linearisation point of the last solve on return (p->xbar is
  * ignored).  loglik, obj and the gradients refer to that last linear problem
  * with its linearisation point held fixed. */
@@ -176,6 +185,19 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* Measurement hook (no effect on results).  map_profile_enable(n) creates n
+ * pairs of HIP events (0 disables and releases them); while enabled, each
+ * kernel the library launches is bracketed by one pair recorded on its
+ * stream, until the n pairs are used up (map_profile_reset rewinds).
+ * map_profile_read waits for the recorded events and returns, for one kernel
+ * kind, the number of timed launches and their summed duration in ms.
+ * Kinds: 0 filter up-sweep, 1 filter fix-up, 2 fused filter fix-up +
+ * trajectory up-sweep, 3 trajectory up-sweep from stored S, v, 4 trajectory
+ * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing). */
+map_status map_profile_enable(int32_t capacity);
+map_status map_profile_reset(void);
+map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms);
 
 const char* map_last_error(void);
 int32_t map_abi_version(void);

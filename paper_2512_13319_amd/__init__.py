@@ -7,8 +7,12 @@ stream, and wraps the fused scans in a `torch.autograd.Function`.  Every step
 of the computation runs in the library's HIP kernels; there is no fallback,
 so a missing library raises.
 
-Layouts (see include/mapscan.h): state-indexed outputs are [components,
-n_states] planes; symmetric matrices are nx(nx+1)/2 lower-triangle planes.
+Layouts (see include/mapscan.h): the library reads and writes every
+state-indexed array (measurements, step lengths, linearisation states, filter
+and smoother moments) in a tiled layout whose tiles match the kernels'
+64-lane x 16-state work units; `to_tiled` / `from_tiled` convert from / to
+natural [components, n_states] planes.  Symmetric matrices are nx(nx+1)/2
+lower-triangle components.
 """
 from __future__ import annotations
 
@@ -22,9 +26,47 @@ from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
-           "MapError", "N_THETA"]
+           "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel"]
 
 N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5}
+TILE = 1024      # states per tile: 64 lanes x 16 states
+LANES, CHUNK = 64, 16
+
+
+def n_tiles(n_states: int) -> int:
+    return (n_states + TILE - 1) // TILE
+
+
+def tiled_numel(n_states: int, comps: int) -> int:
+    return n_tiles(n_states) * comps * TILE
+
+
+def to_tiled(x: torch.Tensor) -> torch.Tensor:
+    """[C, n_states] natural planes -> flat tiled buffer (zero padded)."""
+    C, n = x.shape
+    nt = n_tiles(n)
+    xp = x.new_zeros(C, nt * TILE)
+    xp[:, :n] = x
+    return xp.view(C, nt, LANES, CHUNK).permute(1, 0, 3, 2).contiguous().view(-1)
+
+
+def from_tiled(buf: torch.Tensor, comps: int, n_states: int) -> torch.Tensor:
+    """flat tiled buffer -> [C, n_states] natural planes (a copy)."""
+    nt = n_tiles(n_states)
+    return buf[:nt * comps * TILE].view(nt, comps, CHUNK, LANES).permute(1, 0, 3, 2).reshape(
+        comps, nt * TILE)[:, :n_states]
+
+
+def steps_to_states(seg_off: np.ndarray, n_states: int, a: np.ndarray) -> np.ndarray:
+    """Step-indexed [C, n_steps] -> state-indexed [C, n_states]: the value of
+    the step that ends at each state; a segment's first state gets 0."""
+    a = np.asarray(a, dtype=np.float64)
+    n_steps = a.shape[-1]
+    k = np.arange(n_steps)
+    seg = np.searchsorted(seg_off, k, side="right") - 1
+    out = np.zeros(a.shape[:-1] + (n_states,))
+    out[..., k + seg + 1] = a
+    return out
 
 
 def _ptr(t):
@@ -75,16 +117,20 @@ class Problem:
         self.n_seg = int(so.shape[0] - 1)
         self.n_steps = int(so[-1])
         self.n_states = self.n_steps + self.n_seg
-        dt_t = t(dt)
-        self.dt = dt_t.reshape(-1)
-        self.y = t(y).reshape(ny, self.n_steps) if self.n_steps > 0 else t(np.zeros((ny, 1)))
+        dt_np = np.asarray(dt.cpu().numpy() if torch.is_tensor(dt) else dt, dtype=np.float64).reshape(-1)
+        if dt_np.size == 1 or np.all(dt_np == dt_np[0]):
+            self.dt = t(dt_np[:1])                        # one shared step length
+        else:
+            self.dt = to_tiled(t(steps_to_states(so, self.n_states, dt_np[None])))
+        y_np = np.asarray(y.cpu().numpy() if torch.is_tensor(y) else y, dtype=np.float64)
+        self.y = to_tiled(t(steps_to_states(so, self.n_states, y_np.reshape(ny, self.n_steps))))
         m0 = t(m0)
         P0 = t(P0)
         self.m0 = m0.reshape(-1, nx)
         self.P0 = P0.reshape(-1, nx, nx)
         self.n_theta = N_THETA[model]
         self.theta = None if theta is None else t(theta).reshape(-1, self.n_theta)
-        self.xbar = None if xbar is None else t(xbar).reshape(nx, self.n_states)
+        self.xbar = None if xbar is None else to_tiled(t(xbar).reshape(nx, self.n_states))
         self.lin = None
         if lin is not None:
             self.lin = {}
@@ -127,7 +173,8 @@ class Problem:
         self.struct = s
 
     def set_xbar(self, xbar):
-        self.xbar = xbar.to(self.device, self.dtype).reshape(self.nx, self.n_states).contiguous()
+        """xbar: natural [nx, n_states]."""
+        self.xbar = to_tiled(xbar.to(self.device, self.dtype).reshape(self.nx, self.n_states))
         self._sync_struct()
 
     def set_theta(self, theta):
@@ -152,6 +199,22 @@ class Problem:
     def _empty(self, *shape, dtype=None):
         return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
 
+    def _tiled(self, comps):
+        """Uninitialised tiled buffer for a state-indexed output."""
+        return self._empty(tiled_numel(self.n_states, comps))
+
+    def natural(self, buf, comps):
+        return None if buf is None else from_tiled(buf, comps, self.n_states)
+
+
+def _nat(p, r, natural):
+    """Replace tiled outputs by natural [C, n_states] planes when asked."""
+    if not natural:
+        return r
+    comps = dict(S=p.nsym, v=p.nx, m=p.nx, P=p.nsym, xs=p.nx, Ps=p.nsym, xbar=p.nx)
+    return {k: (p.natural(v, comps[k]) if (k in comps and v is not None) else v)
+            for k, v in r.items()}
+
 
 def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None):
     """Device-resident Problem from a `workloads.Workload`-like object."""
@@ -160,48 +223,51 @@ def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None):
                    lin=getattr(wl, "lin", None), dtype=dtype, device=device)
 
 
-def build_elements(p: Problem):
+def build_elements(p: Problem, natural=True):
+    """Elements of every state as [A (nx*nx), b, C (sym), eta, J (sym)] components."""
     lib = _lib.load()
     n = p.nx * p.nx + 2 * p.nx + 2 * p.nsym
-    out = p._empty(n, p.n_states)
+    out = p._tiled(n)
     _lib.check(lib.map_build_elements(ctypes.byref(p.struct), _ptr(out), _stream()))
-    return out
+    return p.natural(out, n) if natural else out
 
 
-def filter_scan(p: Problem, moments=False, loglik=True):
+def filter_scan(p: Problem, moments=False, loglik=True, natural=True):
     lib = _lib.load()
     ws = p.workspace()
-    S = p._empty(p.nsym, p.n_states)
-    v = p._empty(p.nx, p.n_states)
-    m = p._empty(p.nx, p.n_states) if moments else None
-    P = p._empty(p.nsym, p.n_states) if moments else None
+    S = p._tiled(p.nsym)
+    v = p._tiled(p.nx)
+    m = p._tiled(p.nx) if moments else None
+    P = p._tiled(p.nsym) if moments else None
     ll = p._empty(p.n_seg, dtype=torch.float64) if loglik else None
     _lib.check(lib.map_filter_scan(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(m), _ptr(P),
                                    _ptr(ll), _ptr(ws), ws.numel(), _stream()))
-    return dict(S=S, v=v, m=m, P=P, loglik=ll)
+    return _nat(p, dict(S=S, v=v, m=m, P=P, loglik=ll), natural)
 
 
-def smoother_scan(p: Problem, S, v, covariances=True, objective=True):
+def smoother_scan(p: Problem, S, v, covariances=True, objective=True, natural=True):
+    """S, v: tiled buffers as returned by filter_scan(..., natural=False)."""
     lib = _lib.load()
     ws = p.workspace()
-    xs = p._empty(p.nx, p.n_states)
-    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    xs = p._tiled(p.nx)
+    Ps = p._tiled(p.nsym) if covariances else None
     obj = p._empty(p.n_seg, dtype=torch.float64) if objective else None
     _lib.check(lib.map_smoother_scan(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs),
                                      _ptr(Ps), _ptr(obj), _ptr(ws), ws.numel(), _stream()))
-    return dict(xs=xs, Ps=Ps, obj=obj)
+    return _nat(p, dict(xs=xs, Ps=Ps, obj=obj), natural)
 
 
-def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False, out=None):
+def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False, out=None,
+           natural=True):
     """Fused filter + trajectory scans (+ adjoint when grad).  `out` may carry
-    preallocated buffers (same keys as the result) to avoid allocations."""
+    preallocated tiled buffers (same keys as the result) to avoid allocations."""
     lib = _lib.load()
     ws = p.workspace()
     o = out or {}
-    S = o.get("S") if o.get("S") is not None else p._empty(p.nsym, p.n_states)
-    v = o.get("v") if o.get("v") is not None else p._empty(p.nx, p.n_states)
-    xs = o.get("xs") if o.get("xs") is not None else p._empty(p.nx, p.n_states)
-    Ps = (o.get("Ps") if o.get("Ps") is not None else p._empty(p.nsym, p.n_states)) \
+    S = o.get("S") if o.get("S") is not None else p._tiled(p.nsym)
+    v = o.get("v") if o.get("v") is not None else p._tiled(p.nx)
+    xs = o.get("xs") if o.get("xs") is not None else p._tiled(p.nx)
+    Ps = (o.get("Ps") if o.get("Ps") is not None else p._tiled(p.nsym)) \
         if covariances else None
     f64 = torch.float64
     ll = (o.get("loglik") if o.get("loglik") is not None else p._empty(p.n_seg, dtype=f64)) \
@@ -215,45 +281,48 @@ def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False
     _lib.check(lib.map_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
                               _ptr(ll), _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
                               _stream()))
-    return dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm)
+    return _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm),
+                natural)
 
 
 def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, loglik=True,
-                       objective=True, grad=False):
+                       objective=True, grad=False, natural=True):
+    """xbar0: natural [nx, n_states] or None (m0 of each segment)."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
-    xb = p._empty(p.nx, p.n_states)
-    S = p._empty(p.nsym, p.n_states)
-    v = p._empty(p.nx, p.n_states)
-    xs = p._empty(p.nx, p.n_states)
-    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    xb = p._tiled(p.nx)
+    S = p._tiled(p.nsym)
+    v = p._tiled(p.nx)
+    xs = p._tiled(p.nx)
+    Ps = p._tiled(p.nsym) if covariances else None
     ll = p._empty(p.n_seg, dtype=f64) if loglik else None
     obj = p._empty(p.n_seg, dtype=f64) if objective else None
     gl = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
     gm = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
-    x0 = None if xbar0 is None else xbar0.to(p.device, p.dtype).contiguous()
+    x0 = None if xbar0 is None else to_tiled(xbar0.to(p.device, p.dtype))
     _lib.check(lib.map_iterated_nonlinear(ctypes.byref(p.struct), int(n_iter), _ptr(x0), _ptr(xb),
                                           _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps), _ptr(ll),
                                           _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
                                           _stream()))
-    return dict(xbar=xb, S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm)
+    return _nat(p, dict(xbar=xb, S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl,
+                        g_obj=gm), natural)
 
 
-def backward(p: Problem, S, v, covariances=True, objective=True):
-    """Adjoint from saved filter moments: recomputes the trajectory and returns
-    d loglik / d theta and d obj / d theta per segment."""
+def backward(p: Problem, S, v, covariances=True, objective=True, natural=True):
+    """Adjoint from saved (tiled) filter moments: recomputes the trajectory and
+    returns d loglik / d theta and d obj / d theta per segment."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
-    xs = p._empty(p.nx, p.n_states)
-    Ps = p._empty(p.nsym, p.n_states) if covariances else None
+    xs = p._tiled(p.nx)
+    Ps = p._tiled(p.nsym) if covariances else None
     obj = p._empty(p.n_seg, dtype=f64) if objective else None
     gl = p._empty(p.n_seg, p.n_theta, dtype=f64)
     gm = p._empty(p.n_seg, p.n_theta, dtype=f64)
     _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
                                 _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(), _stream()))
-    return dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm)
+    return _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm), natural)
 
 
 class MapSmooth(torch.autograd.Function):
@@ -268,7 +337,7 @@ class MapSmooth(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, problem: Problem):
         problem.set_theta(theta.detach())
-        r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True)
+        r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True, natural=True)
         ctx.save_for_backward(r["g_loglik"], r["g_obj"])
         ctx.theta_shape = theta.shape
         ctx.theta_dtype = theta.dtype

@@ -21,6 +21,9 @@ FLAGS = [
     # packed-FP32 VALU forms are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wno-unused-result",
+    # lets the compiler drop multiplications by the structural zeros of the
+    # model matrices (no infinities or NaNs are ever produced on purpose)
+    "-fno-signed-zeros", "-ffinite-math-only",
 ]
 
 

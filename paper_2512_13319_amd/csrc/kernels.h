@@ -33,6 +33,17 @@ namespace ms {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+constexpr int kChunk = 16;                   // states per lane
+constexpr int64_t kTile = kWave * kChunk;    // states per wavefront tile
+
+// Tiled layout of every state-indexed array with C components: tile
+// (i / 1024) holds C blocks of 1024 values; inside a block, value of state i
+// sits at (i % 16) * 64 + (i / 16) % 64.  Iteration t of a wavefront (lane l
+// owns states 16 l .. 16 l + 15 of its tile) then touches 64 consecutive
+// addresses per component.
+MS_DEV int64_t tix(int64_t i, int64_t c, int64_t C) {
+  return ((i >> 10) * C + c) * kTile + ((i & (kChunk - 1)) << 6) + ((i >> 4) & (kWave - 1));
+}
 
 template <int N> struct Sym { static constexpr int n = N * (N + 1) / 2; };
 template <int N> struct ElemSz { static constexpr int n = N * N + 2 * N + 2 * Sym<N>::n; };
@@ -82,6 +93,44 @@ MS_DEVONLY void load_mat(const T* base, int64_t ld, int64_t i, T (&a)[N][M], int
   for (int r = 0; r < N; ++r)
 #pragma unroll
     for (int q = 0; q < M; ++q) a[r][q] = base[(c0 + r * M + q) * ld + i];
+}
+
+// tiled state-indexed I/O (C = components of the buffer, c0 = first one written)
+template <typename T, int N>
+MS_DEVONLY void tstore_sym(T* base, int C, int64_t i, const T (&a)[N][N], int c0 = 0) {
+  int c = c0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) base[tix(i, c++, C)] = a[r][q];
+}
+template <typename T, int N>
+MS_DEVONLY void tload_sym(const T* base, int C, int64_t i, T (&a)[N][N], int c0 = 0) {
+  int c = c0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) {
+      a[r][q] = base[tix(i, c++, C)];
+      a[q][r] = a[r][q];
+    }
+}
+template <typename T, int N>
+MS_DEVONLY void tstore_vec(T* base, int C, int64_t i, const T (&a)[N], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) base[tix(i, c0 + r, C)] = a[r];
+}
+template <typename T, int N>
+MS_DEVONLY void tload_vec(const T* base, int C, int64_t i, T (&a)[N], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) a[r] = base[tix(i, c0 + r, C)];
+}
+template <typename T, int N, int M>
+MS_DEVONLY void tstore_mat(T* base, int C, int64_t i, const T (&a)[N][M], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < M; ++q) base[tix(i, c0 + r * M + q, C)] = a[r][q];
 }
 
 // element planes: A (N*N), b (N), C (sym), eta (N), J (sym)
@@ -188,14 +237,14 @@ struct Cursor {
   // Model terms and measurement of the step that ends at (non-head) state i.
   MS_DEVONLY void step(const Prob<T>& p, int64_t i, Step<T, NX, NY, NW>& st, T (&y)[NY]) const {
     const int64_t k = i - s - 1;  // step index
-    const T dt = p.dt[k * p.dt_stride];
+    const T dt = p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0];
 #pragma unroll
-    for (int c = 0; c < NY; ++c) y[c] = p.y[c * p.n_steps + k];
+    for (int c = 0; c < NY; ++c) y[c] = p.y[tix(i, c, NY)];
     if constexpr (M::NTH > 0) {
       T xb[NX];
       if constexpr (M::kNonlinear) {
 #pragma unroll
-        for (int c = 0; c < NX; ++c) xb[c] = p.xbar[c * p.n_states + i];
+        for (int c = 0; c < NX; ++c) xb[c] = p.xbar[tix(i, c, NX)];
       } else {
 #pragma unroll
         for (int c = 0; c < NX; ++c) xb[c] = T(0);
@@ -247,7 +296,7 @@ struct Cursor {
   MS_DEVONLY void xbar(const Prob<T>& p, int64_t i, T (&xb)[NX]) const {
     if constexpr (M::kNonlinear) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) xb[c] = p.xbar[c * p.n_states + i];
+      for (int c = 0; c < NX; ++c) xb[c] = p.xbar[tix(i, c, NX)];
     } else {
 #pragma unroll
       for (int c = 0; c < NX; ++c) xb[c] = T(0);
@@ -478,6 +527,7 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
 // --------------------------------------------------------------------------- pass A
 template <typename T, class M, int L>
 __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
+  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -582,6 +632,7 @@ MS_DEVONLY double pred_loglik(const T (&Sp)[N][N], const T (&vp)[N], const Step<
 
 template <typename T, class M, int L, int kMode>
 __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, FilterOut fo, Acc acc) {
+  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr bool kFilter = kMode != kModeTrajOnly;
   constexpr bool kTraj = kMode != kModeFilter;
@@ -658,22 +709,19 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
 #pragma unroll
           for (int r = 0; r < N; ++r) v[r] = vn[r];
         }
-        store_sym(So, ns, i, S);
-        store_vec(vo, ns, i, v);
+        tstore_sym(So, Sym<N>::n, i, S);
+        tstore_vec(vo, N, i, v);
         if (mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
           mv(Pm, v, mm_);
-          store_vec(mo, ns, i, mm_);
-          store_sym(Po, ns, i, Pm);
+          tstore_vec(mo, N, i, mm_);
+          tstore_sym(Po, Sym<N>::n, i, Pm);
         }
       } else {
         // trajectory maps from stored filter moments
-        load_sym(So, ns, i, S);
-        load_vec(vo, ns, i, v);
-        if (t > 0) {
-          // handled below with the element of state i
-        }
+        tload_sym(So, Sym<N>::n, i, S);
+        tload_vec(vo, N, i, v);
       }
       if constexpr (!kFilter) {
         // map of state i needs the element of state i+1
@@ -756,6 +804,7 @@ struct TrajOut {
 
 template <typename T, class M, int L, bool kGrad>
 __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajOut to, Acc acc) {
+  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
   constexpr int KV = 1 + 2 * NTH;
@@ -796,8 +845,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
     seg_acc = cur.s;
     for (int64_t i = il; i >= j0; --i) {
       T S[N][N], v[N];
-      load_sym(Si, ns, i, S);
-      load_vec(vi, ns, i, v);
+      tload_sym(Si, Sym<N>::n, i, S);
+      tload_vec(vi, N, i, v);
       if (cur.is_last(i)) {
         spd_inv(S, P);
         mv(P, v, x);
@@ -943,8 +992,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
           }
         }
       }
-      store_vec(xo, ns, i, x);
-      if (Po != nullptr) store_sym(Po, ns, i, P);
+      tstore_vec(xo, N, i, x);
+      if (Po != nullptr) tstore_sym(Po, Sym<N>::n, i, P);
       if (cur.is_head(i)) {
         if (to.want_obj) {
           T S0[N][N], v0[N], m0[N], P0i[N][N];
@@ -993,12 +1042,25 @@ __global__ void __launch_bounds__(kBlock) k_build_elements(Prob<T> p, T* out) {
     fresh_from_step(st, y, f);
     fresh_to_elem(f, e);
   }
-  store_elem(out, p.n_states, i, e);
+  constexpr int C = ElemSz<N>::n;
+  tstore_mat(out, C, i, e.A, 0);
+  tstore_vec(out, C, i, e.b, N * N);
+  tstore_sym(out, C, i, e.C, N * N + N);
+  tstore_vec(out, C, i, e.eta, N * N + N + Sym<N>::n);
+  tstore_sym(out, C, i, e.J, N * N + 2 * N + Sym<N>::n);
 }
 
-static __global__ void __launch_bounds__(kBlock) k_zero(double* a, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    a[i] = 0.0;
+// Zero the per-segment accumulators that a pass adds into atomically.
+static __global__ void __launch_bounds__(kBlock) k_zero_acc(Acc a, int64_t n_seg, int64_t nth) {
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_seg; i += stride) {
+    if (a.loglik) a.loglik[i] = 0.0;
+    if (a.obj) a.obj[i] = 0.0;
+  }
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_seg * nth; i += stride) {
+    if (a.g_loglik) a.g_loglik[i] = 0.0;
+    if (a.g_obj) a.g_obj[i] = 0.0;
+  }
 }
 
 }  // namespace ms

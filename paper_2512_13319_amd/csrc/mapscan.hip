@@ -4,6 +4,7 @@
 #include <stdio.h>
 
 #include <string>
+#include <vector>
 
 #include "models.h"
 #include "runner.h"
@@ -12,6 +13,35 @@ namespace ms {
 
 __global__ void k_clear_words(unsigned int* w, int n) {
   if (int(threadIdx.x) < n) w[threadIdx.x] = 0u;
+}
+
+// ---------------------------------------------------------------- profiling hook
+// When enabled, every kernel launch is bracketed by two HIP events recorded on
+// the launch stream.  Events are created once (no device memory is involved).
+namespace prof {
+struct Rec {
+  hipEvent_t a, b;
+  int kind;
+};
+static std::vector<Rec> g_recs;
+static size_t g_used = 0;
+static bool g_on = false;
+static int g_open_kind = -1;
+}  // namespace prof
+
+void prof_begin(int kind, hipStream_t st) {
+  if (!prof::g_on || prof::g_used >= prof::g_recs.size()) return;
+  prof::Rec& r = prof::g_recs[prof::g_used];
+  r.kind = kind;
+  hipEventRecord(r.a, st);
+  prof::g_open_kind = kind;
+}
+
+void prof_end(int kind, hipStream_t st) {
+  if (!prof::g_on || prof::g_open_kind != kind || prof::g_used >= prof::g_recs.size()) return;
+  hipEventRecord(prof::g_recs[prof::g_used].b, st);
+  ++prof::g_used;
+  prof::g_open_kind = -1;
 }
 
 namespace {
@@ -291,6 +321,48 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
                g_loglik, g_obj, ws, static_cast<hipStream_t>(stream)};
   return dispatch(*p, DoSmoother{*p, a, true});
+}
+
+map_status map_profile_enable(int32_t capacity) {
+  for (auto& r : prof::g_recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  prof::g_recs.clear();
+  prof::g_used = 0;
+  prof::g_on = capacity > 0;
+  for (int32_t i = 0; i < capacity; ++i) {
+    prof::Rec r;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+      prof::g_on = false;
+      return fail(MAP_E_HIP, "map_profile_enable: hipEventCreate failed");
+    }
+    r.kind = -1;
+    prof::g_recs.push_back(r);
+  }
+  return MAP_OK;
+}
+
+map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms) {
+  if (count == nullptr || total_ms == nullptr) return fail(MAP_E_ARG, "count/total_ms is NULL");
+  *count = 0;
+  *total_ms = 0.0;
+  for (size_t i = 0; i < prof::g_used; ++i) {
+    const prof::Rec& r = prof::g_recs[i];
+    if (r.kind != kind) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(MAP_E_HIP, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return fail(MAP_E_HIP, "hipEventElapsedTime failed");
+    *count += 1;
+    *total_ms += ms;
+  }
+  return MAP_OK;
+}
+
+map_status map_profile_reset(void) {
+  prof::g_used = 0;
+  return MAP_OK;
 }
 
 const char* map_last_error(void) { return g_err.c_str(); }

@@ -8,8 +8,6 @@
 
 namespace ms {
 
-constexpr int kChunk = 16;  // states per lane
-
 struct WsLayout {
   int64_t n_lanes;   // padded to whole tiles
   int64_t n_tiles;
@@ -20,8 +18,9 @@ struct WsLayout {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz) {
+  constexpr int64_t kChunkStates = 16;
   WsLayout w;
-  const int64_t nl = (n_states + kChunk - 1) / kChunk;
+  const int64_t nl = (n_states + kChunkStates - 1) / kChunkStates;
   w.n_tiles = (nl + 63) / 64;
   w.n_lanes = w.n_tiles * 64;
   const int64_t sym = nx * (nx + 1) / 2;
@@ -57,6 +56,20 @@ struct SmoothArgs {
   void* ws;
   hipStream_t stream;
 };
+
+// Profiling hook: kernel kinds timed by HIP events when enabled.
+enum ProfKind : int {
+  kProfFilterUp = 0,
+  kProfFilterDown = 1,
+  kProfFused = 2,
+  kProfTrajUp = 3,
+  kProfTrajDown = 4,
+  kProfTrajDownGrad = 5,
+  kProfAux = 6,
+  kProfKinds = 7
+};
+void prof_begin(int kind, hipStream_t st);
+void prof_end(int kind, hipStream_t st);
 
 template <typename T, class M>
 struct Runner {

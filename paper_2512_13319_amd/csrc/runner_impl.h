@@ -58,11 +58,14 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base) {
 
 inline unsigned grid_for(int64_t n_tiles) { return unsigned((n_tiles + 3) / 4); }
 
-inline hipError_t zero(double* a, int64_t n, hipStream_t st) {
-  if (a == nullptr || n <= 0) return hipSuccess;
+inline hipError_t zero(const Acc& a, int64_t n_seg, int64_t nth, hipStream_t st) {
+  if (!a.loglik && !a.obj && !a.g_loglik && !a.g_obj) return hipSuccess;
+  const int64_t n = n_seg * (nth > 1 ? nth : 1);
   const int64_t nb = (n + kBlock - 1) / kBlock;
   const unsigned g = unsigned(nb < 1024 ? nb : 1024);
-  k_zero<<<g, kBlock, 0, st>>>(a, n);
+  prof_begin(kProfAux, st);
+  k_zero_acc<<<g, kBlock, 0, st>>>(a, n_seg, nth);
+  prof_end(kProfAux, st);
   return hipGetLastError();
 }
 
@@ -75,7 +78,7 @@ __global__ void __launch_bounds__(kBlock) k_init_xbar(Prob<T> p, int nx, T* xb) 
     int64_t mid = (lo + hi + 1) >> 1;
     if (p.seg_off[mid] + mid <= i) lo = mid; else hi = mid - 1;
   }
-  for (int c = 0; c < nx; ++c) xb[c * p.n_states + i] = p.m0[lo * p.m0_stride + c];
+  for (int c = 0; c < nx; ++c) xb[tix(i, c, nx)] = p.m0[lo * p.m0_stride + c];
 }
 
 #define MS_CHECK(x)                         \
@@ -104,13 +107,17 @@ template <typename T, class M>
 hipError_t Runner<T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Prob<T> p = make_prob<T>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
-  MS_CHECK(zero(a.loglik, q.n_seg, a.stream));
+  MS_CHECK(zero(Acc{a.loglik, nullptr, nullptr, nullptr}, q.n_seg, M::NTH, a.stream));
   const unsigned g = grid_for(w.n_tiles);
+  prof_begin(kProfFilterUp, a.stream);
   k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
   Acc acc{a.loglik, nullptr, nullptr, nullptr};
+  prof_begin(kProfFilterDown, a.stream);
   k_filter_down<T, M, kChunk, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  prof_end(kProfFilterDown, a.stream);
   return hipGetLastError();
 }
 
@@ -119,25 +126,28 @@ hipError_t Runner<T, M>::smoother(const map_problem& q, const SmoothArgs& a, boo
   Prob<T> p = make_prob<T>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
   const int64_t nth = M::NTH;
-  MS_CHECK(zero(a.obj, q.n_seg, a.stream));
-  if (grad) {
-    MS_CHECK(zero(a.g_loglik, q.n_seg * nth, a.stream));
-    MS_CHECK(zero(a.g_obj, q.n_seg * nth, a.stream));
-  }
+  MS_CHECK(zero(Acc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
+                q.n_seg, nth, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   FilterOut fo{a.S, a.v, nullptr, nullptr, 0};
   Acc acc{nullptr, a.obj, a.g_loglik, a.g_obj};
+  prof_begin(kProfTrajUp, a.stream);
   k_filter_down<T, M, kChunk, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  prof_end(kProfTrajUp, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
   if constexpr (M::kAdjoint) {
     if (grad) {
+      prof_begin(kProfTrajDownGrad, a.stream);
       k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      prof_end(kProfTrajDownGrad, a.stream);
       return hipGetLastError();
     }
   }
   to.want_grad = 0;
+  prof_begin(kProfTrajDown, a.stream);
   k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  prof_end(kProfTrajDown, a.stream);
   return hipGetLastError();
 }
 
@@ -147,28 +157,32 @@ hipError_t Runner<T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
   const int64_t nth = M::NTH;
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
-  MS_CHECK(zero(a.loglik, q.n_seg, a.stream));
-  MS_CHECK(zero(a.obj, q.n_seg, a.stream));
-  if (grad) {
-    MS_CHECK(zero(a.g_loglik, q.n_seg * nth, a.stream));
-    MS_CHECK(zero(a.g_obj, q.n_seg * nth, a.stream));
-  }
+  MS_CHECK(zero(Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
+                q.n_seg, nth, a.stream));
   const unsigned g = grid_for(w.n_tiles);
+  prof_begin(kProfFilterUp, a.stream);
   k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
   Acc acc{a.loglik, a.obj, a.g_loglik, a.g_obj};
+  prof_begin(kProfFused, a.stream);
   k_filter_down<T, M, kChunk, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  prof_end(kProfFused, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
   if constexpr (M::kAdjoint) {
     if (grad) {
+      prof_begin(kProfTrajDownGrad, a.stream);
       k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      prof_end(kProfTrajDownGrad, a.stream);
       return hipGetLastError();
     }
   }
   to.want_grad = 0;
+  prof_begin(kProfTrajDown, a.stream);
   k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  prof_end(kProfTrajDown, a.stream);
   return hipGetLastError();
 }
 

@@ -95,9 +95,11 @@ def test_filter_moments_and_separate_smoother(dtype):
     wl = CASES["cv_batched"]().rounded(dtype)
     o = cref.smooth(wl)
     p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
-    f = ms.filter_scan(p, moments=True, loglik=True)
-    s = ms.smoother_scan(p, f["S"], f["v"], covariances=True, objective=True)
+    ft = ms.filter_scan(p, moments=True, loglik=True, natural=False)
+    s = ms.smoother_scan(p, ft["S"], ft["v"], covariances=True, objective=True)
     torch.cuda.synchronize()
+    f = {k: (p.natural(v, p.nsym if k in ("S", "P") else p.nx) if k != "loglik" else v)
+         for k, v in ft.items()}
     tol = TOL[dtype]
     assert rel_err(planes_T(f["m"]), o["m"]) <= tol
     assert rel_err(sym_full(ms, f["P"], wl.nx), o["P"]) <= tol
