@@ -77,7 +77,15 @@ typedef enum {
   MAP_E_UNSUPPORTED = -8  /* model/dimension combination not built */
 } map_status;
 
-typedef enum { MAP_F32 = 0, MAP_F64 = 1 } map_dtype;
+/* Storage and arithmetic precision.  On MI355X, FP64 and (non-packed) FP32
+ * vector FMAs issue at the same rate, so MAP_F32 keeps the caller's arrays in
+ * FP32 (half the HBM traffic) and computes in FP64: the information-form
+ * recursion cancels large terms (v = S m for states far from the origin), and
+ * FP64 arithmetic keeps the FP32 results at FP32 rounding level.  MAP_F32_FAST
+ * also computes in FP32 (fewer registers, higher occupancy); its error grows
+ * with |x| / (dt |dx/dt|) and can exceed 1e-4 relative on long trajectories.
+ * The workspace is kept in the arithmetic type. */
+typedef enum { MAP_F32 = 0, MAP_F64 = 1, MAP_F32_FAST = 2 } map_dtype;
 
 /* Models.  Parameter vectors theta (per segment):
  *   MAP_MODEL_LINEAR    none; dense F, c, L, W, H, r, R given per step (forward only)
@@ -98,7 +106,7 @@ typedef enum {
 
 typedef struct {
   int32_t nx, ny, nw;      /* state, measurement and driving-noise dimensions */
-  int32_t dtype;           /* map_dtype of every real input/output array */
+  int32_t dtype;           /* map_dtype: storage (and arithmetic) precision of the arrays */
   int32_t model;           /* map_model */
   int32_t n_theta;         /* must equal the model's parameter count (0 for LINEAR) */
   int64_t n_seg;           /* number of trajectories, >= 1 */

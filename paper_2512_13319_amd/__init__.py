@@ -26,7 +26,7 @@ from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
-           "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel"]
+           "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
 N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5}
 TILE = 1024      # states per tile: 64 lanes x 16 states
@@ -102,13 +102,19 @@ class Problem:
     xbar      [nx, n_states] linearisation states (nonlinear models)
     lin       dict of F, c, L, W, H, r, R for the linear model: each either one
               matrix or a leading per-step axis
+    dtype     storage precision of every array (torch.float64 or torch.float32)
+    arith     arithmetic precision: "f64" (default; with float32 storage this is
+              the accurate FP32 mode) or "f32" (float32 storage only)
     """
 
     def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
-                 dtype=torch.float64, device="cuda"):
+                 dtype=torch.float64, device="cuda", arith="f64"):
         _lib.load()
         self.model, self.nx, self.ny, self.nw = model, nx, ny, nw
         self.dtype, self.device = dtype, torch.device(device)
+        if arith not in ("f64", "f32") or (arith == "f32" and dtype != torch.float32):
+            raise ValueError("arith must be 'f64', or 'f32' with float32 storage")
+        self.arith = arith
         t = lambda a: None if a is None else torch.as_tensor(a).to(self.device, dtype).contiguous()
         so = np.ascontiguousarray(np.asarray(seg_off if not torch.is_tensor(seg_off)
                                              else seg_off.cpu().numpy(), dtype=np.int64))
@@ -147,7 +153,8 @@ class Problem:
     def _sync_struct(self):
         s = _lib.MapProblem()
         s.nx, s.ny, s.nw = self.nx, self.ny, self.nw
-        s.dtype = _lib.MAP_F64 if self.dtype == torch.float64 else _lib.MAP_F32
+        s.dtype = (_lib.MAP_F64 if self.dtype == torch.float64 else
+                   _lib.MAP_F32_FAST if self.arith == "f32" else _lib.MAP_F32)
         s.model = MODELS[self.model]
         s.n_theta = self.n_theta
         s.n_seg, s.n_steps = self.n_seg, self.n_steps
@@ -216,11 +223,11 @@ def _nat(p, r, natural):
             for k, v in r.items()}
 
 
-def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None):
+def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, arith="f64"):
     """Device-resident Problem from a `workloads.Workload`-like object."""
     return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
                    theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
-                   lin=getattr(wl, "lin", None), dtype=dtype, device=device)
+                   lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith)
 
 
 def build_elements(p: Problem, natural=True):
@@ -323,6 +330,40 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True):
     _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
                                 _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(), _stream()))
     return _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm), natural)
+
+
+class GraphedSmooth:
+    """The fused launch sequence of `smooth` captured once into a HIP graph
+    (torch.cuda.CUDAGraph on ROCm) with fixed output buffers, then replayed.
+    Inputs are read from the Problem's device buffers at replay time, so
+    refreshing their contents in place (same shapes) is seen by the next
+    replay.  The sequence contains kernel launches only (the accumulators are
+    cleared by a kernel, not by memset nodes)."""
+
+    def __init__(self, p: Problem, covariances=True, loglik=True, objective=True, grad=False):
+        self.p = p
+        self.kw = dict(covariances=covariances, loglik=loglik, objective=objective, grad=grad)
+        f64 = torch.float64
+        self.out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx),
+                        Ps=p._tiled(p.nsym) if covariances else None,
+                        loglik=p._empty(p.n_seg, dtype=f64) if loglik else None,
+                        obj=p._empty(p.n_seg, dtype=f64) if objective else None,
+                        g_loglik=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None,
+                        g_obj=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None)
+        p.workspace()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            smooth(p, out=self.out, natural=False, **self.kw)   # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            smooth(p, out=self.out, natural=False, **self.kw)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
 
 
 class MapSmooth(torch.autograd.Function):

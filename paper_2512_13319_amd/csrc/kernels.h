@@ -96,41 +96,42 @@ MS_DEVONLY void load_mat(const T* base, int64_t ld, int64_t i, T (&a)[N][M], int
 }
 
 // tiled state-indexed I/O (C = components of the buffer, c0 = first one written)
-template <typename T, int N>
-MS_DEVONLY void tstore_sym(T* base, int C, int64_t i, const T (&a)[N][N], int c0 = 0) {
+// (P = storage type of the buffer, T = compute type of the registers)
+template <typename P, typename T, int N>
+MS_DEVONLY void tstore_sym(P* base, int C, int64_t i, const T (&a)[N][N], int c0 = 0) {
   int c = c0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int q = 0; q <= r; ++q) base[tix(i, c++, C)] = a[r][q];
+    for (int q = 0; q <= r; ++q) base[tix(i, c++, C)] = P(a[r][q]);
 }
-template <typename T, int N>
-MS_DEVONLY void tload_sym(const T* base, int C, int64_t i, T (&a)[N][N], int c0 = 0) {
+template <typename P, typename T, int N>
+MS_DEVONLY void tload_sym(const P* base, int C, int64_t i, T (&a)[N][N], int c0 = 0) {
   int c = c0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
     for (int q = 0; q <= r; ++q) {
-      a[r][q] = base[tix(i, c++, C)];
+      a[r][q] = T(base[tix(i, c++, C)]);
       a[q][r] = a[r][q];
     }
 }
-template <typename T, int N>
-MS_DEVONLY void tstore_vec(T* base, int C, int64_t i, const T (&a)[N], int c0 = 0) {
+template <typename P, typename T, int N>
+MS_DEVONLY void tstore_vec(P* base, int C, int64_t i, const T (&a)[N], int c0 = 0) {
 #pragma unroll
-  for (int r = 0; r < N; ++r) base[tix(i, c0 + r, C)] = a[r];
+  for (int r = 0; r < N; ++r) base[tix(i, c0 + r, C)] = P(a[r]);
 }
-template <typename T, int N>
-MS_DEVONLY void tload_vec(const T* base, int C, int64_t i, T (&a)[N], int c0 = 0) {
+template <typename P, typename T, int N>
+MS_DEVONLY void tload_vec(const P* base, int C, int64_t i, T (&a)[N], int c0 = 0) {
 #pragma unroll
-  for (int r = 0; r < N; ++r) a[r] = base[tix(i, c0 + r, C)];
+  for (int r = 0; r < N; ++r) a[r] = T(base[tix(i, c0 + r, C)]);
 }
-template <typename T, int N, int M>
-MS_DEVONLY void tstore_mat(T* base, int C, int64_t i, const T (&a)[N][M], int c0 = 0) {
+template <typename P, typename T, int N, int M>
+MS_DEVONLY void tstore_mat(P* base, int C, int64_t i, const T (&a)[N][M], int c0 = 0) {
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int q = 0; q < M; ++q) base[tix(i, c0 + r * M + q, C)] = a[r][q];
+    for (int q = 0; q < M; ++q) base[tix(i, c0 + r * M + q, C)] = P(a[r][q]);
 }
 
 // element planes: A (N*N), b (N), C (sym), eta (N), J (sym)
@@ -202,7 +203,8 @@ struct Acc {
 };
 
 // --------------------------------------------------------------------------- model access
-template <typename T, class M>
+// TS: storage type of the problem's arrays; T: compute type.
+template <typename TS, typename T, class M>
 struct Cursor {
   static constexpr int NX = M::NX, NY = M::NY, NW = M::NW;
   static constexpr int NTH_ = M::NTH > 0 ? M::NTH : 1;
@@ -211,16 +213,16 @@ struct Cursor {
   int64_t next_head;  // first state of the next segment (n_states after the last)
   T th[NTH_];
 
-  MS_DEVONLY void load_seg(const Prob<T>& p) {
+  MS_DEVONLY void load_seg(const Prob<TS>& p) {
     head = p.seg_off[s] + s;
     next_head = p.seg_off[s + 1] + s + 1;
     if constexpr (M::NTH > 0) {
 #pragma unroll
-      for (int t = 0; t < M::NTH; ++t) th[t] = p.theta[s * p.th_stride + t];
+      for (int t = 0; t < M::NTH; ++t) th[t] = T(p.theta[s * p.th_stride + t]);
     }
   }
   // segment containing state i (0 <= i < n_states)
-  MS_DEVONLY void init(const Prob<T>& p, int64_t i) {
+  MS_DEVONLY void init(const Prob<TS>& p, int64_t i) {
     int64_t lo = 0, hi = p.n_seg - 1;
     while (lo < hi) {
       int64_t mid = (lo + hi + 1) >> 1;
@@ -229,22 +231,39 @@ struct Cursor {
     s = lo;
     load_seg(p);
   }
-  MS_DEVONLY void next(const Prob<T>& p) { ++s; load_seg(p); }
-  MS_DEVONLY void prev(const Prob<T>& p) { --s; load_seg(p); }
+  MS_DEVONLY void next(const Prob<TS>& p) { ++s; load_seg(p); }
+  MS_DEVONLY void prev(const Prob<TS>& p) { --s; load_seg(p); }
   MS_DEVONLY bool is_head(int64_t i) const { return i == head; }
   MS_DEVONLY bool is_last(int64_t i) const { return i + 1 == next_head; }
 
-  // Model terms and measurement of the step that ends at (non-head) state i.
-  MS_DEVONLY void step(const Prob<T>& p, int64_t i, Step<T, NX, NY, NW>& st, T (&y)[NY]) const {
-    const int64_t k = i - s - 1;  // step index
-    const T dt = p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0];
+  // The per-state inputs of the step that ends at state i (measurement, step
+  // length, linearisation state).  Loads only, so that a loop can issue them
+  // one state ahead of their use; valid for any i < n_states (the values of a
+  // segment's first state are simply not used).
+  struct Raw {
+    T dt;
+    T y[NY];
+    T xb[M::kNonlinear ? NX : 1];
+  };
+  MS_DEVONLY void fetch(const Prob<TS>& p, int64_t i, Raw& r) const {
+    r.dt = T(p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0]);
 #pragma unroll
-    for (int c = 0; c < NY; ++c) y[c] = p.y[tix(i, c, NY)];
+    for (int c = 0; c < NY; ++c) r.y[c] = T(p.y[tix(i, c, NY)]);
+    if constexpr (M::kNonlinear) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) r.xb[c] = T(p.xbar[tix(i, c, NX)]);
+    }
+  }
+
+  // Model terms of the step that ends at (non-head) state i from its fetched inputs.
+  MS_DEVONLY void terms(const Prob<TS>& p, int64_t i, const Raw& r, Step<T, NX, NY, NW>& st) const {
+    const int64_t k = i - s - 1;  // step index
+    const T dt = r.dt;
     if constexpr (M::NTH > 0) {
       T xb[NX];
       if constexpr (M::kNonlinear) {
 #pragma unroll
-        for (int c = 0; c < NX; ++c) xb[c] = p.xbar[tix(i, c, NX)];
+        for (int c = 0; c < NX; ++c) xb[c] = r.xb[c];
       } else {
 #pragma unroll
         for (int c = 0; c < NX; ++c) xb[c] = T(0);
@@ -252,13 +271,13 @@ struct Cursor {
       M::terms(th, xb, dt, st);
     } else {
       st.dt = dt;
-      const T* F = p.F + k * p.sF;
-      const T* c = p.c + k * p.sc;
-      const T* L = p.L + k * p.sL;
-      const T* W = p.W + k * p.sW;
-      const T* H = p.H + k * p.sH;
-      const T* r = p.r + k * p.sr;
-      const T* R = p.R + k * p.sR;
+      const TS* F = p.F + k * p.sF;
+      const TS* c = p.c + k * p.sc;
+      const TS* L = p.L + k * p.sL;
+      const TS* W = p.W + k * p.sW;
+      const TS* H = p.H + k * p.sH;
+      const TS* r = p.r + k * p.sr;
+      const TS* R = p.R + k * p.sR;
 #pragma unroll
       for (int a = 0; a < NX; ++a) {
 #pragma unroll
@@ -293,10 +312,18 @@ struct Cursor {
     }
   }
 
-  MS_DEVONLY void xbar(const Prob<T>& p, int64_t i, T (&xb)[NX]) const {
+  MS_DEVONLY void step(const Prob<TS>& p, int64_t i, Step<T, NX, NY, NW>& st, T (&y)[NY]) const {
+    Raw r;
+    fetch(p, i, r);
+    terms(p, i, r, st);
+#pragma unroll
+    for (int c = 0; c < NY; ++c) y[c] = r.y[c];
+  }
+
+  MS_DEVONLY void xbar(const Prob<TS>& p, int64_t i, T (&xb)[NX]) const {
     if constexpr (M::kNonlinear) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) xb[c] = p.xbar[tix(i, c, NX)];
+      for (int c = 0; c < NX; ++c) xb[c] = T(p.xbar[tix(i, c, NX)]);
     } else {
 #pragma unroll
       for (int c = 0; c < NX; ++c) xb[c] = T(0);
@@ -304,14 +331,14 @@ struct Cursor {
   }
 
   // prior of the current segment: S0 = P0^{-1}, v0 = P0^{-1} m0
-  MS_DEVONLY void prior(const Prob<T>& p, T (&S0)[NX][NX], T (&v0)[NX], T (&m0)[NX],
+  MS_DEVONLY void prior(const Prob<TS>& p, T (&S0)[NX][NX], T (&v0)[NX], T (&m0)[NX],
                         T (&P0i)[NX][NX]) const {
     T P0[NX][NX];
 #pragma unroll
     for (int a = 0; a < NX; ++a) {
-      m0[a] = p.m0[s * p.m0_stride + a];
+      m0[a] = T(p.m0[s * p.m0_stride + a]);
 #pragma unroll
-      for (int b = 0; b < NX; ++b) P0[a][b] = p.P0[s * p.P0_stride + a * NX + b];
+      for (int b = 0; b < NX; ++b) P0[a][b] = T(p.P0[s * p.P0_stride + a * NX + b]);
     }
     spd_inv(P0, P0i);
     mcopy(P0i, S0);
@@ -327,7 +354,7 @@ MS_DEVONLY void flush_wave(int64_t seg, double (&val)[K], double* const (&dst)[K
                            const int64_t (&stride)[K]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int sg = int(seg);
-#pragma unroll
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
     const int src = lane + d < kWave ? lane + d : lane;
     const int so = shfl(sg, src);
@@ -390,7 +417,7 @@ MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
     combine(acc, o, tmp);
     acc = tmp;
   }
-#pragma unroll
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
     shfl_elem(o, acc, lane >= d ? lane - d : lane);
     if (lane >= d) {
@@ -472,7 +499,7 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
     aff_append(acc, o);
   }
   // reverse inclusive scan: acc <- acc o (lanes to the right)
-#pragma unroll
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
     shfl_aff(o, acc, lane + d < kWave ? lane + d : lane);
     if (lane + d < kWave) aff_append(acc, o);
@@ -525,8 +552,8 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
 }
 
 // --------------------------------------------------------------------------- pass A
-template <typename T, class M, int L>
-__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
+template <typename TS, typename T, class M, int L>
+__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX;
   const int lane = threadIdx.x & (kWave - 1);
@@ -536,11 +563,15 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
   Elem<T, N> agg;
   elem_identity(agg);
   if (j0 < p.n_states) {
-    Cursor<T, M> cur;
+    Cursor<TS, T, M> cur;
     cur.init(p, j0);
+    typename Cursor<TS, T, M>::Raw rn;
+    cur.fetch(p, j0, rn);
     for (int t = 0; t < L; ++t) {
       const int64_t i = j0 + t;
       if (i >= p.n_states) break;
+      const typename Cursor<TS, T, M>::Raw rc = rn;
+      if (t + 1 < L && i + 1 < p.n_states) cur.fetch(p, i + 1, rn);  // one state ahead
       if (cur.is_head(i)) {
         T m0[N], P0i[N][N];
         cur.prior(p, agg.J, agg.eta, m0, P0i);
@@ -550,10 +581,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
         for (int r = 0; r < N; ++r) agg.b[r] = T(0);
       } else {
         Step<T, N, M::NY, M::NW> st;
-        T y[M::NY];
-        cur.step(p, i, st, y);
+        cur.terms(p, i, rc, st);
         Fresh<T, N, M::NW> f;
-        fresh_from_step(st, y, f);
+        fresh_from_step(st, rc.y, f);
         fold_fresh(agg, f);
       }
       if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
@@ -561,7 +591,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<T> p, Ws<T> ws) {
   }
   // in-tile inclusive scan
   Elem<T, N> o, tmp;
-#pragma unroll
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
     shfl_elem(o, agg, lane >= d ? lane - d : lane);
     if (lane >= d) {
@@ -630,8 +660,8 @@ MS_DEVONLY double pred_loglik(const T (&Sp)[N][N], const T (&vp)[N], const Step<
   return -0.5 * (double(NY) * 1.8378770664093453 + 2.0 * ::log(det) + q);
 }
 
-template <typename T, class M, int L, int kMode>
-__global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, FilterOut fo, Acc acc) {
+template <typename TS, typename T, class M, int L, int kMode>
+__global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, FilterOut fo, Acc acc) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr bool kFilter = kMode != kModeTrajOnly;
@@ -641,10 +671,10 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
   const int64_t ns = p.n_states;
-  T* So = static_cast<T*>(fo.S);
-  T* vo = static_cast<T*>(fo.v);
-  T* mo = static_cast<T*>(fo.m);
-  T* Po = static_cast<T*>(fo.P);
+  TS* So = static_cast<TS*>(fo.S);
+  TS* vo = static_cast<TS*>(fo.v);
+  TS* mo = static_cast<TS*>(fo.m);
+  TS* Po = static_cast<TS*>(fo.P);
   T S[N][N], v[N];
   if constexpr (kFilter) {
     if (tile < ws.n_tiles) {
@@ -660,12 +690,21 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
   double ll = 0.0;
   int64_t seg_acc = -1;
   if (j0 < ns) {
-    Cursor<T, M> cur;
+    Cursor<TS, T, M> cur;
     cur.init(p, j0);
     seg_acc = cur.s;
+    typename Cursor<TS, T, M>::Raw rn;
+    cur.fetch(p, kFilter ? j0 : min<int64_t>(j0 + 1, ns - 1), rn);
     for (int t = 0; t < L; ++t) {
       const int64_t i = j0 + t;
       if (i >= ns) break;
+      // inputs of state i (filter) or of state i + 1 (trajectory maps only),
+      // with the next ones requested one state ahead
+      const typename Cursor<TS, T, M>::Raw rc = rn;
+      {
+        const int64_t nxt = kFilter ? i + 1 : i + 2;
+        if (nxt < ns && nxt <= j0 + L) cur.fetch(p, nxt, rn);
+      }
       if constexpr (kFilter) {
         if (cur.is_head(i)) {
           if (kTraj && t > 0) {
@@ -688,8 +727,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
           cur.prior(p, S, v, m0, P0i);
         } else {
           Step<T, N, NY, NW> st;
-          T y[NY];
-          cur.step(p, i, st, y);
+          const T(&y)[NY] = rc.y;
+          cur.terms(p, i, rc, st);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
@@ -733,10 +772,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
           aff_append(sagg, G, beta, Lam);
         } else {
           Step<T, N, NY, NW> st;
-          T y[NY];
-          cur.step(p, i + 1, st, y);
+          cur.terms(p, i + 1, rc, st);
           Fresh<T, N, NW> f;
-          fresh_from_step(st, y, f);
+          fresh_from_step(st, rc.y, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           aff_append(sagg, G, beta, Lam);
@@ -754,11 +792,12 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
         mv(Lam, v, beta);
         aff_append(sagg, G, beta, Lam);
       } else {
+        // il + 1 = j0 + L here (a chunk cut short ends the sequence), and its
+        // inputs were fetched in the last iteration
         Step<T, N, NY, NW> st;
-        T y[NY];
-        cur.step(p, il + 1, st, y);
+        cur.terms(p, il + 1, rn, st);
         Fresh<T, N, NW> f;
-        fresh_from_step(st, y, f);
+        fresh_from_step(st, rn.y, f);
         T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
         info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
         aff_append(sagg, G, beta, Lam);
@@ -776,7 +815,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<T> p, Ws<T> ws, Fil
   if constexpr (kTraj) {
     // reverse in-tile scan of the trajectory maps
     Aff<T, N> o;
-#pragma unroll
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
     for (int d = 1; d < kWave; d <<= 1) {
       shfl_aff(o, sagg, lane + d < kWave ? lane + d : lane);
       if (lane + d < kWave) aff_append(sagg, o);
@@ -802,8 +841,8 @@ struct TrajOut {
   int want_grad;
 };
 
-template <typename T, class M, int L, bool kGrad>
-__global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajOut to, Acc acc) {
+template <typename TS, typename T, class M, int L, bool kGrad>
+__global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, TrajOut to, Acc acc) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
@@ -812,10 +851,10 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
   const int64_t ns = p.n_states;
-  const T* Si = static_cast<const T*>(to.S);
-  const T* vi = static_cast<const T*>(to.v);
-  T* xo = static_cast<T*>(to.xs);
-  T* Po = static_cast<T*>(to.Ps);
+  const TS* Si = static_cast<const TS*>(to.S);
+  const TS* vi = static_cast<const TS*>(to.v);
+  TS* xo = static_cast<TS*>(to.xs);
+  TS* Po = static_cast<TS*>(to.Ps);
   T x[N], P[N][N];
   if (tile < ws.n_tiles) {
     load_vec(ws.stile_carry, ws.n_tiles, tile, x, 0);
@@ -840,20 +879,34 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
   int64_t seg_acc = -1;
   if (j0 < ns) {
     const int64_t il = min<int64_t>(j0 + L, ns) - 1;
-    Cursor<T, M> cur;
+    Cursor<TS, T, M> cur;
     cur.init(p, il);
     seg_acc = cur.s;
+    // filter moments of state i and inputs of state i + 1, requested one
+    // iteration ahead of their use
+    T Sn_[N][N], vn_[N];
+    typename Cursor<TS, T, M>::Raw rn;
+    tload_sym(Si, Sym<N>::n, il, Sn_);
+    tload_vec(vi, N, il, vn_);
+    cur.fetch(p, il + 1 < ns ? il + 1 : il, rn);
     for (int64_t i = il; i >= j0; --i) {
       T S[N][N], v[N];
-      tload_sym(Si, Sym<N>::n, i, S);
-      tload_vec(vi, N, i, v);
+      mcopy(Sn_, S);
+#pragma unroll
+      for (int a = 0; a < N; ++a) v[a] = vn_[a];
+      const typename Cursor<TS, T, M>::Raw rc = rn;
+      if (i > j0) {
+        tload_sym(Si, Sym<N>::n, i - 1, Sn_);
+        tload_vec(vi, N, i - 1, vn_);
+        cur.fetch(p, i, rn);
+      }
       if (cur.is_last(i)) {
         spd_inv(S, P);
         mv(P, v, x);
       } else {
         Step<T, N, NY, NW> st;
-        T y[NY];
-        cur.step(p, i + 1, st, y);
+        const T(&y)[NY] = rc.y;
+        cur.terms(p, i + 1, rc, st);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
         // trajectory map of state i (shares Z with the information step)
@@ -978,7 +1031,13 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
                 GRm[a][b] = T(-0.5) * st.dt * sRe;
               }
             T xb[N];
-            cur.xbar(p, i + 1, xb);
+            if constexpr (M::kNonlinear) {
+#pragma unroll
+              for (int a = 0; a < N; ++a) xb[a] = rc.xb[a];
+            } else {
+#pragma unroll
+              for (int a = 0; a < N; ++a) xb[a] = T(0);
+            }
             double gl[NTH], gm[NTH];
 #pragma unroll
             for (int t = 0; t < NTH; ++t) gl[t] = gm[t] = 0.0;
@@ -1019,12 +1078,12 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<T> p, Ws<T> ws, TrajO
 }
 
 // --------------------------------------------------------------------------- misc
-template <typename T, class M>
-__global__ void __launch_bounds__(kBlock) k_build_elements(Prob<T> p, T* out) {
+template <typename TS, typename T, class M>
+__global__ void __launch_bounds__(kBlock) k_build_elements(Prob<TS> p, TS* out) {
   constexpr int N = M::NX;
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= p.n_states) return;
-  Cursor<T, M> cur;
+  Cursor<TS, T, M> cur;
   cur.init(p, i);
   Elem<T, N> e;
   if (cur.is_head(i)) {

@@ -91,8 +91,9 @@ template <class Fn>
 map_status dispatch(const map_problem& p, Fn&& f) {
 #define MS_CASE(MODEL, NX, NY, NW, NTH, M)                                            \
   if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) {                   \
-    if (p.dtype == MAP_F64) return f.template run<double, M>();                       \
-    return f.template run<float, M>();                                                \
+    if (p.dtype == MAP_F64) return f.template run<double, double, M>();               \
+    if (p.dtype == MAP_F32) return f.template run<float, double, M>();                \
+    return f.template run<float, float, M>();                                         \
   }
   MS_MODELS(MS_CASE)
 #undef MS_CASE
@@ -113,7 +114,8 @@ bool model_nonlinear(int model) { return model == MAP_MODEL_VDP || model == MAP_
 map_status validate(const map_problem* pp, bool need_xbar = true) {
   if (pp == nullptr) return fail(MAP_E_ARG, "problem is NULL");
   const map_problem& p = *pp;
-  if (p.dtype != MAP_F32 && p.dtype != MAP_F64) return fail(MAP_E_DTYPE, "unknown dtype %d", p.dtype);
+  if (p.dtype != MAP_F32 && p.dtype != MAP_F64 && p.dtype != MAP_F32_FAST)
+    return fail(MAP_E_DTYPE, "unknown dtype %d", p.dtype);
   if (p.nx < 1 || p.nx > 8 || p.ny < 1 || p.ny > 8 || p.nw < 1 || p.nw > 8)
     return fail(MAP_E_DIM, "dimensions (nx, ny, nw) = (%d, %d, %d) outside [1, 8]", p.nx, p.ny, p.nw);
   if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_LORENZ63)
@@ -158,8 +160,11 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
   return MAP_OK;
 }
 
+size_t compute_bytes(int dtype) { return dtype == MAP_F32_FAST ? 4 : 8; }
+size_t storage_bytes(int dtype) { return dtype == MAP_F64 ? 8 : 4; }
+
 map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
-  const size_t need = ws_layout(p.nx, p.n_steps + p.n_seg, p.dtype == MAP_F64 ? 8 : 4).total;
+  const size_t need = ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype)).total;
   if (ws == nullptr) return fail(MAP_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < need)
     return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -170,38 +175,38 @@ struct DoBuild {
   const map_problem& p;
   void* elems;
   hipStream_t st;
-  template <typename T, class M> map_status run() {
-    return hip_status(Runner<T, M>::build(p, elems, st), "map_build_elements");
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::build(p, elems, st), "map_build_elements");
   }
 };
 struct DoFilter {
   const map_problem& p;
   SmoothArgs a;
-  template <typename T, class M> map_status run() {
-    return hip_status(Runner<T, M>::filter(p, a), "map_filter_scan");
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::filter(p, a), "map_filter_scan");
   }
 };
 struct DoSmoother {
   const map_problem& p;
   SmoothArgs a;
   bool grad;
-  template <typename T, class M> map_status run() {
-    return hip_status(Runner<T, M>::smoother(p, a, grad), grad ? "map_backward" : "map_smoother_scan");
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::smoother(p, a, grad), grad ? "map_backward" : "map_smoother_scan");
   }
 };
 struct DoSmooth {
   const map_problem& p;
   SmoothArgs a;
-  template <typename T, class M> map_status run() {
-    return hip_status(Runner<T, M>::smooth(p, a), "map_smooth");
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::smooth(p, a), "map_smooth");
   }
 };
 struct DoInitX {
   const map_problem& p;
   void* xb;
   hipStream_t st;
-  template <typename T, class M> map_status run() {
-    return hip_status(Runner<T, M>::init_xbar(p, xb, st), "map_iterated_nonlinear");
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::init_xbar(p, xb, st), "map_iterated_nonlinear");
   }
 };
 
@@ -214,7 +219,7 @@ extern "C" {
 
 size_t map_workspace_bytes(const map_problem* p) {
   if (validate(p, false) != MAP_OK) return 0;
-  return ws_layout(p->nx, p->n_steps + p->n_seg, p->dtype == MAP_F64 ? 8 : 4).total;
+  return ws_layout(p->nx, p->n_steps + p->n_seg, compute_bytes(p->dtype)).total;
 }
 
 map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream) {
@@ -282,7 +287,8 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t ns = p->n_steps + p->n_seg;
-  const size_t bytes = size_t(p->nx) * size_t(ns) * (p->dtype == MAP_F64 ? 8 : 4);
+  const size_t tiles = size_t((ns + 1023) / 1024);
+  const size_t bytes = size_t(p->nx) * tiles * 1024 * storage_bytes(p->dtype);
   // iteration i reads xbar from `src` and writes xs to the other buffer; the
   // last iteration must read xbar_buf and write xs
   void* bufs[2] = {xbar_buf, xs};

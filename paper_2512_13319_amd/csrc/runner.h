@@ -71,7 +71,8 @@ enum ProfKind : int {
 void prof_begin(int kind, hipStream_t st);
 void prof_end(int kind, hipStream_t st);
 
-template <typename T, class M>
+// TS: storage type of the caller's arrays; T: arithmetic (and workspace) type.
+template <typename TS, typename T, class M>
 struct Runner {
   static hipError_t build(const map_problem& p, void* elems, hipStream_t st);
   static hipError_t filter(const map_problem& p, const SmoothArgs& a);

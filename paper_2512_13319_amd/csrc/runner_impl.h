@@ -87,43 +87,43 @@ __global__ void __launch_bounds__(kBlock) k_init_xbar(Prob<T> p, int nx, T* xb) 
     if (e_ != hipSuccess) return e_;        \
   } while (0)
 
-template <typename T, class M>
-hipError_t Runner<T, M>::build(const map_problem& q, void* elems, hipStream_t st) {
-  Prob<T> p = make_prob<T>(q);
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::build(const map_problem& q, void* elems, hipStream_t st) {
+  Prob<TS> p = make_prob<TS>(q);
   const unsigned g = unsigned((p.n_states + kBlock - 1) / kBlock);
-  k_build_elements<T, M><<<g, kBlock, 0, st>>>(p, static_cast<T*>(elems));
+  k_build_elements<TS, T, M><<<g, kBlock, 0, st>>>(p, static_cast<TS*>(elems));
   return hipGetLastError();
 }
 
-template <typename T, class M>
-hipError_t Runner<T, M>::init_xbar(const map_problem& q, void* xbar, hipStream_t st) {
-  Prob<T> p = make_prob<T>(q);
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::init_xbar(const map_problem& q, void* xbar, hipStream_t st) {
+  Prob<TS> p = make_prob<TS>(q);
   const unsigned g = unsigned((p.n_states + kBlock - 1) / kBlock);
-  k_init_xbar<T><<<g, kBlock, 0, st>>>(p, M::NX, static_cast<T*>(xbar));
+  k_init_xbar<TS><<<g, kBlock, 0, st>>>(p, M::NX, static_cast<TS*>(xbar));
   return hipGetLastError();
 }
 
-template <typename T, class M>
-hipError_t Runner<T, M>::filter(const map_problem& q, const SmoothArgs& a) {
-  Prob<T> p = make_prob<T>(q);
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
+  Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
   MS_CHECK(zero(Acc{a.loglik, nullptr, nullptr, nullptr}, q.n_seg, M::NTH, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
   Acc acc{a.loglik, nullptr, nullptr, nullptr};
   prof_begin(kProfFilterDown, a.stream);
-  k_filter_down<T, M, kChunk, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kChunk, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfFilterDown, a.stream);
   return hipGetLastError();
 }
 
-template <typename T, class M>
-hipError_t Runner<T, M>::smoother(const map_problem& q, const SmoothArgs& a, bool grad) {
-  Prob<T> p = make_prob<T>(q);
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a, bool grad) {
+  Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
   const int64_t nth = M::NTH;
   MS_CHECK(zero(Acc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
@@ -132,28 +132,28 @@ hipError_t Runner<T, M>::smoother(const map_problem& q, const SmoothArgs& a, boo
   FilterOut fo{a.S, a.v, nullptr, nullptr, 0};
   Acc acc{nullptr, a.obj, a.g_loglik, a.g_obj};
   prof_begin(kProfTrajUp, a.stream);
-  k_filter_down<T, M, kChunk, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kChunk, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfTrajUp, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
   if constexpr (M::kAdjoint) {
     if (grad) {
       prof_begin(kProfTrajDownGrad, a.stream);
-      k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      k_traj_down<TS, T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
       prof_end(kProfTrajDownGrad, a.stream);
       return hipGetLastError();
     }
   }
   to.want_grad = 0;
   prof_begin(kProfTrajDown, a.stream);
-  k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  k_traj_down<TS, T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
   prof_end(kProfTrajDown, a.stream);
   return hipGetLastError();
 }
 
-template <typename T, class M>
-hipError_t Runner<T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
-  Prob<T> p = make_prob<T>(q);
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
+  Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
   const int64_t nth = M::NTH;
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
@@ -161,34 +161,35 @@ hipError_t Runner<T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
                 q.n_seg, nth, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
   Acc acc{a.loglik, a.obj, a.g_loglik, a.g_obj};
   prof_begin(kProfFused, a.stream);
-  k_filter_down<T, M, kChunk, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kChunk, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfFused, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
   if constexpr (M::kAdjoint) {
     if (grad) {
       prof_begin(kProfTrajDownGrad, a.stream);
-      k_traj_down<T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+      k_traj_down<TS, T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
       prof_end(kProfTrajDownGrad, a.stream);
       return hipGetLastError();
     }
   }
   to.want_grad = 0;
   prof_begin(kProfTrajDown, a.stream);
-  k_traj_down<T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
+  k_traj_down<TS, T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
   prof_end(kProfTrajDown, a.stream);
   return hipGetLastError();
 }
 
 #define MS_COMMA ,
 #define MS_INSTANTIATE(M)                 \
-  template struct Runner<float, M>;       \
-  template struct Runner<double, M>;
+  template struct Runner<double, double, M>; \
+  template struct Runner<float, double, M>;  \
+  template struct Runner<float, float, M>;
 
 }  // namespace ms

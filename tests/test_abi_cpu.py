@@ -76,7 +76,9 @@ def test_workspace_bytes(seg):
     n = lib.map_workspace_bytes(ctypes.byref(p))
     assert n > 0
     p2 = good(seg)
-    p2.dtype = _lib.MAP_F32
+    p2.dtype = _lib.MAP_F32          # FP32 storage, FP64 arithmetic: FP64 workspace
+    assert lib.map_workspace_bytes(ctypes.byref(p2)) == n
+    p2.dtype = _lib.MAP_F32_FAST     # FP32 arithmetic: FP32 workspace
     assert 0 < lib.map_workspace_bytes(ctypes.byref(p2)) < n
     p2.nx = 9
     assert lib.map_workspace_bytes(ctypes.byref(p2)) == 0

@@ -17,6 +17,10 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-9, "f32": 1e-4}
 TORCH_DT = {"f64": torch.float64, "f32": torch.float32}
+# FP32 storage with FP32 arithmetic: the information vector v = S m cancels
+# large terms when the state is far from the origin; its error grows like
+# eps32 * |x| / (dt * |dx/dt|) and is only bounded, not held to 1e-4.
+TOL_FAST = 2e-3
 
 
 def _mapscan():
@@ -67,6 +71,13 @@ def test_linear_smoother_parity(case, dtype):
     r = ms.smooth(p, covariances=True, loglik=True, objective=True)
     torch.cuda.synchronize()
     tol = TOL[dtype]
+    if dtype == "f32":
+        pf = ms.problem_from_workload(wl, dtype=torch.float32, arith="f32")
+        rf = ms.smooth(pf, covariances=True, loglik=False, objective=False)
+        torch.cuda.synchronize()
+        e_fast = rel_err(planes_T(rf["xs"]), o["xs"])
+        print(f"{case} f32-arith: xs {e_fast:.2e}")
+        assert e_fast <= TOL_FAST
     nx = wl.nx
     e_xs = rel_err(planes_T(r["xs"]), o["xs"])
     e_Ps = rel_err(sym_full(ms, r["Ps"], nx), o["Ps"])
