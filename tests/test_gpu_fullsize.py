@@ -5,7 +5,7 @@ state by state against the C oracle.  cfg4 (4096 ragged segments, ~1.6e7
 steps) and cfg5 (256 Lorenz-63 trajectories of 2^14 steps, 5 iterations) run
 in full on the GPU; segments are independent, so the oracle recomputes a
 sample of them (always including the shortest and the longest) and those
-are compared one by one.  cfg5 gradients are checked against central
+are compared one by one.  cfg5 gradients are checked against five-point central
 differences of the oracle's log-likelihood and objective with the
 linearisation point held fixed.
 """
@@ -125,24 +125,27 @@ def test_cfg5_full_lorenz_with_gradients():
                    o["Ps"])
     print(f"cfg5: xs {e_xs:.2e} Ps {e_Ps:.2e}")
     assert e_xs <= 1e-9 and e_Ps <= 1e-9
-    # gradients on the last linear problem (linearisation point frozen) by
-    # central differences of the oracle, for the first sampled segment
+    # gradients on the last linear problem (linearisation point frozen) by a
+    # five-point central-difference stencil of the oracle, for the first
+    # sampled segment.  The log-likelihood is ~2e5 in magnitude, so a plain
+    # two-point difference with a tiny step loses ~1e-5 to cancellation; the
+    # fourth-order stencil at h = 3e-3 |theta_i| is accurate to ~1e-8.
     one, _ = sub_workload(wl, segs[:1])
     xbar = o["xbar"][:, : one.n_states]
     gl = r["g_loglik"].cpu().numpy()[segs[0]]
     gm = r["g_obj"].cpu().numpy()[segs[0]]
     th = one.theta[0].copy()
     for i in range(th.size):
-        h = 1e-6 * abs(th[i])
-        vals = []
-        for sgn in (1, -1):
+        h = 3e-3 * abs(th[i])
+        vals = {}
+        for k in (-2, -1, 1, 2):
             w = workloads.Workload(**{**one.__dict__})
             w.theta = one.theta.copy()
-            w.theta[0, i] = th[i] + sgn * h
+            w.theta[0, i] = th[i] + k * h
             oo = cref.smooth(w, xbar)
-            vals.append((oo["loglik"][0], oo["mstar"][0]))
-        fd_l = (vals[0][0] - vals[1][0]) / (2 * h)
-        fd_m = (vals[0][1] - vals[1][1]) / (2 * h)
+            vals[k] = (oo["loglik"][0], oo["mstar"][0])
+        fd_l, fd_m = ((-vals[2][j] + 8 * vals[1][j] - 8 * vals[-1][j] + vals[-2][j]) / (12 * h)
+                      for j in (0, 1))
         print(f"cfg5 theta[{i}]: dl {gl[i]:.10e} fd {fd_l:.10e}  dM {gm[i]:.10e} fd {fd_m:.10e}")
         assert abs(gl[i] - fd_l) <= 1e-6 * max(1.0, abs(fd_l))
         assert abs(gm[i] - fd_m) <= 1e-6 * max(1.0, abs(fd_m))
