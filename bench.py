@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "smoothed time-steps/sec (fwd+adjoint) at nx=4, T=2^20, vs plain scan; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}  # packed FP32 is not generated
+# both storage modes compute in FP64 (FP32 storage is converted on load), so
+# the FP64 vector peak applies to either
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
 
 
 def cpu_info():
@@ -38,6 +40,29 @@ def cpu_info():
     except OSError:
         pass
     return model
+
+
+def library_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2512_13319_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_record(dtype):
+    """Per-launch counter figures of the scan kernels on this workload
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device-copy calibration,
+    SQ_INSTS_VALU_FLOPS_FP64 checked against a multiply of known size), and
+    whether they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters_cv4_T2p20_%s.json" % dtype)
+    if not os.path.exists(path):
+        return None, False
+    with open(path) as fh:
+        rec = json.load(fh)
+    return rec, rec.get("source_sha256_16") == library_source_hash()
 
 
 def kernel_bytes(nx, ny, s, kind):
@@ -58,7 +83,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"],
+                    help="storage type of inputs and outputs (arithmetic is FP64 in both)")
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6144)
@@ -147,13 +173,29 @@ def main():
     dom = max((k for k in kern_fa if k != "aux"), key=lambda k: kern_fa[k][1])
     dom_ms = kern_fa[dom][1]
     bytes_dom = kernel_bytes(p.nx, p.ny, s, dom) * p.n_states
-    achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
+    hbm_gbs = bytes_dom / (dom_ms * 1e-3) / 1e9
     step_bytes = (p.ny + 2 * (nsym + p.nx) + p.nx + nsym) * s * p.n_states
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom, "kernel_ms": round(dom_ms, 4),
-                "kernels_ms": {k: round(v[1], 4) for k, v in kern_fa.items()},
-                "step_hbm_frac": round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    rec, fresh = counter_record(args.dtype)
+    kc = (rec or {}).get("kernels", {}).get(dom)
+    if kc is not None and kc.get("n_states") == p.n_states:
+        # FP64 VALU roof: the per-state flop count of the kernel (counted, see
+        # the counter record) over its measured launch duration
+        flops = kc["flops_fp64_per_state"] * p.n_states
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],
+                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS[args.dtype], 4),
+                    "traffic": kc["hbm_bytes"] if fresh else None,
+                    "flops_per_state": kc["flops_fp64_per_state"],
+                    "counters_current": fresh}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roofline.update({
+        "kernel": dom, "kernel_ms": round(dom_ms, 4),
+        "kernels_ms": {k: round(v[1], 4) for k, v in kern_fa.items()},
+        "hbm_algorithmic": {"bytes": bytes_dom, "achieved_GBs": round(hbm_gbs, 1),
+                            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)},
+        "step_hbm_frac": round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
 
     res = {
         "metric": METRIC,
@@ -166,12 +208,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2-D constant-velocity SDE nx=4 ny=2, T=2^%d steps dt=1e-3, q=0.5, "
                                "r=0.05, one trajectory; filter + smoother (x*, P^s) + log-lik + "
                                "objective + adjoint d/d(gamma,q,r)" % args.log2T,
-                   "T": T, "nx": 4, "ny": 2, "n_seg": 1},
+                   "T": T, "nx": 4, "ny": 2, "n_seg": 1, "storage": args.dtype},
         "plain_scan": {"value": T / (ms_pl * 1e-3), "ms_per_step": ms_pl,
                        "kernels_ms": {k: round(v[1], 4) for k, v in kern_pl.items()}},
         "wall_ms_per_step": round(wall_fa, 4),
@@ -181,13 +223,17 @@ def main():
     }
 
     if args.copy_calibration:
-        # plain device-to-device copy of a known size, read and written once
+        # plain device-to-device copy of a known size, read and written once,
+        # and an FP64 multiply of a known number of elements (one flop each)
         nbytes = 256 << 20
         a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
+        x = torch.full((1 << 24,), 1.5, dtype=torch.float64, device=dev)
+        x.mul_(1.0000001)
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = nbytes
+        res["flop_calibration_fp64"] = 1 << 24
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(res))

@@ -45,6 +45,38 @@ MS_DEV int64_t tix(int64_t i, int64_t c, int64_t C) {
   return ((i >> 10) * C + c) * kTile + ((i & (kChunk - 1)) << 6) + ((i >> 4) & (kWave - 1));
 }
 
+// One past the last state of lane g, whose states start at 16 g: lane g runs
+// states 16 g .. 16 g + 15, the sequence's last work lane also runs whatever
+// follows (a short final tile merged into the work tile before it; n_lanes
+// counts work lanes), and a lane past the work lanes runs none (its range is
+// empty even where 16 g < n_states, i.e. in a merged final tile).
+MS_DEV int64_t lane_end(int64_t g, int64_t n_lanes, int64_t n_states) {
+  const int64_t j0 = g * kChunk;
+  if (g >= n_lanes || j0 >= n_states) return j0;
+  if (g == n_lanes - 1) return n_states;
+  return j0 + kChunk < n_states ? j0 + kChunk : n_states;
+}
+
+// Logical block of this workgroup.  Workgroups are dispatched to the eight
+// XCDs round robin (workgroup b runs on XCD b % 8); the logical order gives
+// each XCD one contiguous range of tiles, so that every XCD streams through
+// contiguous memory instead of every eighth group of tiles of each array (a
+// fixed stride that loaded some XCDs' memory traffic much more than others').
+// A bijection of [0, gridDim.x).
+MS_DEVONLY int64_t logical_block() {
+  constexpr int64_t kXcd = 8;
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % kXcd, k = b / kXcd, q = nb / kXcd, r = nb % kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Wait for every outstanding vector memory operation.  Used once before each
+// state loop: the compiler's waits inside a loop must hold for every path into
+// the loop header, and loads still in flight from before the loop would
+// otherwise make the wait of every iteration stricter than the loop itself
+// needs (down to waiting for the previous state's stores).
+MS_DEVONLY void drain_vmem() { __builtin_amdgcn_s_waitcnt(0); }
+
 template <int N> struct Sym { static constexpr int n = N * (N + 1) / 2; };
 template <int N> struct ElemSz { static constexpr int n = N * N + 2 * N + 2 * Sym<N>::n; };
 template <int N> struct AffSz { static constexpr int n = N * N + N + Sym<N>::n; };
@@ -220,6 +252,13 @@ struct Cursor {
 #pragma unroll
       for (int t = 0; t < M::NTH; ++t) th[t] = T(p.theta[s * p.th_stride + t]);
     }
+    // Every later state uses these values.  Loaded in a branch that runs only
+    // when the segment changes, they would count as possibly outstanding at
+    // every iteration of the state loops, and the compiler would then wait for
+    // all vector memory operations (the prefetched inputs and the stores of
+    // the previous state included) before each state.  Waiting here, once per
+    // segment, keeps that wait out of the loops.
+    __builtin_amdgcn_s_waitcnt(0);
   }
   // segment containing state i (0 <= i < n_states)
   MS_DEVONLY void init(const Prob<TS>& p, int64_t i) {
@@ -410,12 +449,18 @@ MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
   const int64_t nt = ws.n_tiles;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
-  Elem<T, N> acc, tmp, o;
-  elem_identity(acc);
-  for (int64_t t = t0; t < t1; ++t) {
-    load_elem(ws.tile_agg, nt, t, o);
-    combine(acc, o, tmp);
-    acc = tmp;
+  Elem<T, N> acc, tmp, o, nx_;
+  if (t0 < t1) {
+    load_elem(ws.tile_agg, nt, t0, acc);
+    if (t0 + 1 < t1) load_elem(ws.tile_agg, nt, t0 + 1, nx_);
+    for (int64_t t = t0 + 1; t < t1; ++t) {
+      o = nx_;
+      if (t + 1 < t1) load_elem(ws.tile_agg, nt, t + 1, nx_);  // one tile ahead
+      combine(acc, o, tmp);
+      acc = tmp;
+    }
+  } else {
+    elem_identity(acc);
   }
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
@@ -476,11 +521,16 @@ MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
     carry_apply(S, v, o);
   }
   carry_apply(S, v, lx);
+  // carries before this thread's tiles (the one after its last tile is not needed)
+  if (t0 + 1 < t1) load_elem(ws.tile_agg, nt, t0, nx_);
   for (int64_t t = t0; t < t1; ++t) {
     store_sym(ws.tile_carry, nt, t, S, 0);
     store_vec(ws.tile_carry, nt, t, v, Sym<N>::n);
-    load_elem(ws.tile_agg, nt, t, o);
-    carry_apply(S, v, o);
+    if (t + 1 < t1) {
+      o = nx_;
+      if (t + 2 < t1) load_elem(ws.tile_agg, nt, t + 1, nx_);
+      carry_apply(S, v, o);
+    }
   }
 }
 
@@ -492,11 +542,17 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
   const int64_t nt = ws.n_tiles;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
-  Aff<T, N> acc, o;
-  aff_identity(acc);
-  for (int64_t t = t0; t < t1; ++t) {
-    load_aff(ws.stile_agg, nt, t, o);
-    aff_append(acc, o);
+  Aff<T, N> acc, o, nx_;
+  if (t0 < t1) {
+    load_aff(ws.stile_agg, nt, t0, acc);
+    if (t0 + 1 < t1) load_aff(ws.stile_agg, nt, t0 + 1, nx_);
+    for (int64_t t = t0 + 1; t < t1; ++t) {
+      o = nx_;
+      if (t + 1 < t1) load_aff(ws.stile_agg, nt, t + 1, nx_);  // one tile ahead
+      aff_append(acc, o);
+    }
+  } else {
+    aff_identity(acc);
   }
   // reverse inclusive scan: acc <- acc o (lanes to the right)
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
@@ -543,11 +599,16 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
 #pragma unroll
   for (int r = 0; r < N; ++r) x[r] = ex.bt[r];
   mcopy(ex.Om, P);
+  // values after this thread's tiles (the one before its first tile is not needed)
+  if (t1 - 1 > t0) load_aff(ws.stile_agg, nt, t1 - 1, nx_);
   for (int64_t t = t1 - 1; t >= t0; --t) {
     store_vec(ws.stile_carry, nt, t, x, 0);
     store_sym(ws.stile_carry, nt, t, P, N);
-    load_aff(ws.stile_agg, nt, t, o);
-    aff_apply(o, x, P);
+    if (t > t0) {
+      o = nx_;
+      if (t - 1 > t0) load_aff(ws.stile_agg, nt, t - 1, nx_);
+      aff_apply(o, x, P);
+    }
   }
 }
 
@@ -557,21 +618,24 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
+  const int64_t j1 = lane_end(g, ws.n_lanes, p.n_states);
   Elem<T, N> agg;
   elem_identity(agg);
-  if (j0 < p.n_states) {
+  if (j0 < j1) {
     Cursor<TS, T, M> cur;
     cur.init(p, j0);
     typename Cursor<TS, T, M>::Raw rn;
     cur.fetch(p, j0, rn);
-    for (int t = 0; t < L; ++t) {
-      const int64_t i = j0 + t;
-      if (i >= p.n_states) break;
+    drain_vmem();
+    for (int64_t i = j0; i < j1; ++i) {
       const typename Cursor<TS, T, M>::Raw rc = rn;
-      if (t + 1 < L && i + 1 < p.n_states) cur.fetch(p, i + 1, rn);  // one state ahead
+      // one state ahead, always issued (a repeat of state i on the last one):
+      // the same number of loads on every path keeps the compiler's waits
+      // for them exact
+      cur.fetch(p, i + 1 < j1 ? i + 1 : i, rn);
       if (cur.is_head(i)) {
         T m0[N], P0i[N][N];
         cur.prior(p, agg.J, agg.eta, m0, P0i);
@@ -667,10 +731,11 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   constexpr bool kFilter = kMode != kModeTrajOnly;
   constexpr bool kTraj = kMode != kModeFilter;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
   const int64_t ns = p.n_states;
+  const int64_t j1 = lane_end(g, ws.n_lanes, ns);
   TS* So = static_cast<TS*>(fo.S);
   TS* vo = static_cast<TS*>(fo.v);
   TS* mo = static_cast<TS*>(fo.m);
@@ -689,25 +754,27 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   aff_identity(sagg);
   double ll = 0.0;
   int64_t seg_acc = -1;
-  if (j0 < ns) {
+  if (j0 < j1) {
     Cursor<TS, T, M> cur;
     cur.init(p, j0);
     seg_acc = cur.s;
     typename Cursor<TS, T, M>::Raw rn;
     cur.fetch(p, kFilter ? j0 : min<int64_t>(j0 + 1, ns - 1), rn);
-    for (int t = 0; t < L; ++t) {
-      const int64_t i = j0 + t;
-      if (i >= ns) break;
+    drain_vmem();
+    for (int64_t i = j0; i < j1; ++i) {
+      const bool first = i == j0;
       // inputs of state i (filter) or of state i + 1 (trajectory maps only),
       // with the next ones requested one state ahead
       const typename Cursor<TS, T, M>::Raw rc = rn;
       {
+        // always issued, clamped into the sequence (see the filter up-sweep)
         const int64_t nxt = kFilter ? i + 1 : i + 2;
-        if (nxt < ns && nxt <= j0 + L) cur.fetch(p, nxt, rn);
+        const int64_t lim = j1 < ns ? j1 : ns - 1;
+        cur.fetch(p, nxt <= lim ? nxt : lim, rn);
       }
       if constexpr (kFilter) {
         if (cur.is_head(i)) {
-          if (kTraj && t > 0) {
+          if (kTraj && !first) {
             // previous state ends its segment: constant trajectory map
             T G[N][N], beta[N], Lam[N][N];
             mzero(G);
@@ -732,7 +799,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
-          if (kTraj && t > 0) {
+          if (kTraj && !first) {
             info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
             aff_append(sagg, G, beta, Lam);
           } else {
@@ -750,7 +817,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         }
         tstore_sym(So, Sym<N>::n, i, S);
         tstore_vec(vo, N, i, v);
-        if (mo != nullptr) {
+        if (kMode == kModeFilter && mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
           mv(Pm, v, mm_);
@@ -784,7 +851,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
     }
     if constexpr (kFilter && kTraj) {
       // trajectory map of the chunk's last state
-      const int64_t il = min<int64_t>(j0 + L, ns) - 1;
+      const int64_t il = j1 - 1;
       if (il + 1 >= ns || il + 1 == cur.head) {
         T G[N][N], beta[N], Lam[N][N];
         mzero(G);
@@ -792,8 +859,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         mv(Lam, v, beta);
         aff_append(sagg, G, beta, Lam);
       } else {
-        // il + 1 = j0 + L here (a chunk cut short ends the sequence), and its
-        // inputs were fetched in the last iteration
+        // il + 1 = j1 < ns here, and its inputs were fetched in the last
+        // iteration
         Step<T, N, NY, NW> st;
         cur.terms(p, il + 1, rn, st);
         Fresh<T, N, NW> f;
@@ -841,13 +908,13 @@ struct TrajOut {
   int want_grad;
 };
 
-template <typename TS, typename T, class M, int L, bool kGrad>
+template <typename TS, typename T, class M, int L, bool kGrad, bool kCov>
 __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, TrajOut to, Acc acc) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
   constexpr int KV = 1 + 2 * NTH;
-  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
   const int64_t ns = p.n_states;
@@ -877,29 +944,40 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     dstr[1 + t] = dstr[1 + NTH + t] = NTH;
   }
   int64_t seg_acc = -1;
-  if (j0 < ns) {
-    const int64_t il = min<int64_t>(j0 + L, ns) - 1;
+  const int64_t j1 = lane_end(g, ws.n_lanes, ns);
+  if (j0 < j1) {
+    const int64_t il = j1 - 1;
     Cursor<TS, T, M> cur;
     cur.init(p, il);
     seg_acc = cur.s;
-    // filter moments of state i and inputs of state i + 1, requested one
-    // iteration ahead of their use
-    T Sn_[N][N], vn_[N];
-    typename Cursor<TS, T, M>::Raw rn;
-    tload_sym(Si, Sym<N>::n, il, Sn_);
-    tload_vec(vi, N, il, vn_);
-    cur.fetch(p, il + 1 < ns ? il + 1 : il, rn);
-    for (int64_t i = il; i >= j0; --i) {
+    // Filter moments of a state and inputs of the state after it, in three
+    // rotating buffers: this pass streams the most data, so each buffer is
+    // refilled (always issued, clamped into the lane) at the end of the state
+    // that used it, for the state three steps further down, and its loads have
+    // two whole states to arrive.  Each buffer is read in place and refilled
+    // only after its last use, so the loop carries it in the same registers
+    // (a register copy of a buffer would make its loads wait early).
+    struct Ahead {
+      T S[N][N];
+      T v[N];
+      typename Cursor<TS, T, M>::Raw r;
+    } q0, q1, q2;
+    auto refill = [&](int64_t k, Ahead& q) {
+      const int64_t ia = k >= j0 ? k : j0;
+      tload_sym(Si, Sym<N>::n, ia, q.S);
+      tload_vec(vi, N, ia, q.v);
+      cur.fetch(p, ia + 1 < ns ? ia + 1 : ia, q.r);
+    };
+    refill(il, q0);
+    refill(il - 1, q1);
+    refill(il - 2, q2);
+    // one state of the backward walk; q holds state i
+    auto body = [&](int64_t i, Ahead& q) {
       T S[N][N], v[N];
-      mcopy(Sn_, S);
+      mcopy(q.S, S);
 #pragma unroll
-      for (int a = 0; a < N; ++a) v[a] = vn_[a];
-      const typename Cursor<TS, T, M>::Raw rc = rn;
-      if (i > j0) {
-        tload_sym(Si, Sym<N>::n, i - 1, Sn_);
-        tload_vec(vi, N, i - 1, vn_);
-        cur.fetch(p, i, rn);
-      }
+      for (int a = 0; a < N; ++a) v[a] = q.v[a];
+      const typename Cursor<TS, T, M>::Raw rc = q.r;
       if (cur.is_last(i)) {
         spd_inv(S, P);
         mv(P, v, x);
@@ -1052,7 +1130,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
         }
       }
       tstore_vec(xo, N, i, x);
-      if (Po != nullptr) tstore_sym(Po, Sym<N>::n, i, P);
+      if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
       if (cur.is_head(i)) {
         if (to.want_obj) {
           T S0[N][N], v0[N], m0[N], P0i[N][N];
@@ -1072,6 +1150,19 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
           seg_acc = cur.s;
         }
       }
+      refill(i - 3, q);
+    };
+    drain_vmem();
+    int64_t i = il;
+    for (; i - 2 >= j0; i -= 3) {
+      body(i, q0);
+      body(i - 1, q1);
+      body(i - 2, q2);
+    }
+    // the last one or two states (the rotation continues with q0, then q1)
+    for (; i >= j0; --i) {
+      body(i, q0);
+      q0 = q1;
     }
   }
   if (to.want_obj || kGrad) flush_wave<KV>(seg_acc, val, dst, dstr);

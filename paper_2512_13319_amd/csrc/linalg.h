@@ -19,10 +19,69 @@ template <> MS_DEV float fma_<float>(float a, float b, float c) { return __built
 template <typename T> MS_DEV T fabs_(T x);
 template <> MS_DEV double fabs_<double>(double x) { return __builtin_fabs(x); }
 template <> MS_DEV float fabs_<float>(float x) { return __builtin_fabsf(x); }
-template <typename T> MS_DEV T rcp(T x) { return T(1) / x; }
 template <typename T> MS_DEV T sqrt_(T x);
 template <> MS_DEV double sqrt_<double>(double x) { return __builtin_sqrt(x); }
 template <> MS_DEV float sqrt_<float>(float x) { return __builtin_sqrtf(x); }
+
+// Reciprocal and square root on the device: the hardware estimates (v_rcp,
+// v_rsq) refined by iteration rather than the correctly rounded sequences,
+// which are about twice as long on a dependent chain.  Results are within a
+// few ulp, far inside the tolerances the solvers need.
+//   rcp(x):          Newton-Raphson  e = 1 - x y,  y <- y + y e  (the relative
+//                    error squares at each step; two steps in FP64, one in FP32).
+//   sqrt_rsqrt(x):   Goldschmidt's coupled iteration from y ~ x^{-1/2}:
+//                    g = x y, h = y / 2;  r = 1/2 - g h,  g <- g + g r,
+//                    h <- h + h r;  g -> sqrt(x) and 2 h -> 1 / sqrt(x).
+template <typename T> MS_DEV T rcp(T x);
+template <> MS_DEV double rcp<double>(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
+#else
+  return 1.0 / x;
+#endif
+}
+template <> MS_DEV float rcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float y = __builtin_amdgcn_rcpf(x);
+  float e = __builtin_fmaf(-x, y, 1.0f);
+  return __builtin_fmaf(y, e, y);
+#else
+  return 1.0f / x;
+#endif
+}
+// (d, di) = (sqrt(x), 1 / sqrt(x)) for x > 0
+template <typename T> MS_DEV void sqrt_rsqrt(T x, T& d, T& di);
+template <> MS_DEV void sqrt_rsqrt<double>(double x, double& d, double& di) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-g, h, 0.5);
+  d = __builtin_fma(g, r, g);
+  di = 2.0 * __builtin_fma(h, r, h);
+#else
+  d = __builtin_sqrt(x);
+  di = 1.0 / d;
+#endif
+}
+template <> MS_DEV void sqrt_rsqrt<float>(float x, float& d, float& di) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float g = x * y, h = 0.5f * y;
+  const float r = __builtin_fmaf(-g, h, 0.5f);
+  d = __builtin_fmaf(g, r, g);
+  di = 2.0f * __builtin_fmaf(h, r, h);
+#else
+  d = __builtin_sqrtf(x);
+  di = 1.0f / d;
+#endif
+}
 template <typename T> MS_DEV T log_(T x);
 template <> MS_DEV double log_<double>(double x) { return ::log(x); }
 template <> MS_DEV float log_<float>(float x) { return ::logf(x); }
@@ -156,8 +215,8 @@ MS_DEV void chol(const T (&a)[N][N], T (&l)[N][N], T (&dinv)[N]) {
     T s = a[j][j];
 #pragma unroll
     for (int k = 0; k < j; ++k) s = fma_(-l[j][k], l[j][k], s);
-    T d = sqrt_(s);
-    T di = rcp(d);
+    T d, di;
+    sqrt_rsqrt(s, d, di);
     l[j][j] = d;
     dinv[j] = di;
 #pragma unroll

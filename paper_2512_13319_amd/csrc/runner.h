@@ -17,11 +17,23 @@ struct WsLayout {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Work tiles (1024 states, one per wavefront).  A final tile of at most
+// kMergeStates states is not given a wavefront of its own: the last lane of the
+// tile before it runs those states after its own 16 (a grid of 2^k steps has
+// 2^k + 1 states, and a one-state tile would otherwise make a block that can
+// only start once an earlier block has left its compute unit).  The storage
+// layout of state-indexed arrays does not depend on this.
+constexpr int64_t kMergeStates = 8;
+inline int64_t work_tiles(int64_t n_states) {
+  constexpr int64_t kTileStates = 1024;
+  const int64_t full = n_states / kTileStates, rem = n_states % kTileStates;
+  if (full > 0 && rem > 0 && rem <= kMergeStates) return full;
+  return (n_states + kTileStates - 1) / kTileStates;
+}
+
 inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz) {
-  constexpr int64_t kChunkStates = 16;
   WsLayout w;
-  const int64_t nl = (n_states + kChunkStates - 1) / kChunkStates;
-  w.n_tiles = (nl + 63) / 64;
+  w.n_tiles = work_tiles(n_states);
   w.n_lanes = w.n_tiles * 64;
   const int64_t sym = nx * (nx + 1) / 2;
   const int64_t elem = nx * nx + 2 * nx + 2 * sym;

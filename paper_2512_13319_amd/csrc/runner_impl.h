@@ -103,6 +103,32 @@ hipError_t Runner<TS, T, M>::init_xbar(const map_problem& q, void* xbar, hipStre
   return hipGetLastError();
 }
 
+// Trajectory fix-up, instantiated for (adjoint, covariance output).
+template <typename TS, typename T, class M>
+hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const Acc& acc, bool grad,
+                            unsigned g, hipStream_t st) {
+  const bool cov = to.Ps != nullptr;
+  if constexpr (M::kAdjoint) {
+    if (grad) {
+      prof_begin(kProfTrajDownGrad, st);
+      if (cov)
+        k_traj_down<TS, T, M, kChunk, true, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+      else
+        k_traj_down<TS, T, M, kChunk, true, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+      prof_end(kProfTrajDownGrad, st);
+      return hipGetLastError();
+    }
+  }
+  to.want_grad = 0;
+  prof_begin(kProfTrajDown, st);
+  if (cov)
+    k_traj_down<TS, T, M, kChunk, false, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+  else
+    k_traj_down<TS, T, M, kChunk, false, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+  prof_end(kProfTrajDown, st);
+  return hipGetLastError();
+}
+
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
@@ -136,19 +162,7 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
   prof_end(kProfTrajUp, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
-  if constexpr (M::kAdjoint) {
-    if (grad) {
-      prof_begin(kProfTrajDownGrad, a.stream);
-      k_traj_down<TS, T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
-      prof_end(kProfTrajDownGrad, a.stream);
-      return hipGetLastError();
-    }
-  }
-  to.want_grad = 0;
-  prof_begin(kProfTrajDown, a.stream);
-  k_traj_down<TS, T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
-  prof_end(kProfTrajDown, a.stream);
-  return hipGetLastError();
+  return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 
 template <typename TS, typename T, class M>
@@ -171,19 +185,7 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   prof_end(kProfFused, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
-  if constexpr (M::kAdjoint) {
-    if (grad) {
-      prof_begin(kProfTrajDownGrad, a.stream);
-      k_traj_down<TS, T, M, kChunk, true><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
-      prof_end(kProfTrajDownGrad, a.stream);
-      return hipGetLastError();
-    }
-  }
-  to.want_grad = 0;
-  prof_begin(kProfTrajDown, a.stream);
-  k_traj_down<TS, T, M, kChunk, false><<<g, kBlock, 0, a.stream>>>(p, w, to, acc);
-  prof_end(kProfTrajDown, a.stream);
-  return hipGetLastError();
+  return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 
 #define MS_COMMA ,

@@ -58,6 +58,16 @@ CASES = {
     "cv_batched": lambda: workloads.cv_batched(n_seg=37, lmin=2.0, lmax=9.0, seed=13),
     "linear_tv": lambda: workloads.linear_random(T=700, nx=3, ny=2, nw=3, seed=14, n_seg=3),
     "linear_singular": lambda: workloads.linear_random(T=900, nx=4, ny=2, nw=2, seed=15),
+    # 2 * 1024 + 8 states: the 8-state final tile runs on the last lane of the
+    # tile before it (that lane then holds 24 states)
+    "cv_tail8_merged": lambda: workloads.cv(T=2055, d=2, dt=1e-3, q=0.5, r=0.05,
+                                            m0=[5, 5, 0, 0], P0=1e-2 * np.eye(4), seed=16),
+    # 2 * 1024 + 9 states: the final tile keeps a wavefront of its own
+    "cv_tail9_own": lambda: workloads.cv(T=2056, d=2, dt=1e-3, q=0.5, r=0.05,
+                                         m0=[5, 5, 0, 0], P0=1e-2 * np.eye(4), seed=17),
+    # merged final tile that contains three segment heads (states 2035, 2040,
+    # 2042 of 2055), one of them a one-step segment
+    "batched_tail_heads": lambda: workloads.cv_batched(lens=[1500, 533, 4, 1, 12], seed=18),
 }
 
 

@@ -152,11 +152,16 @@ def cv(T=1024, d=1, dt=None, t_end=None, gamma=0.0, q=1.0, r=0.1, m0=None, P0=No
 
 def cv_batched(n_seg=4096, lmin=8.0, lmax=14.0, d=2, dt=1e-3, gamma=0.0,
                qrange=(0.1, 1.0), rrange=(0.01, 0.2), m0=(5, 5, 0, 0), P0=1e-2,
-               seed=4, name="cv_batched") -> Workload:
+               seed=4, name="cv_batched", lens=None) -> Workload:
+    """Segment lengths floor(2^U(lmin, lmax)) steps, or the given `lens`."""
     rng = _rng(seed)
     nx = 2 * d
-    lens = np.floor(2.0 ** rng.uniform(lmin, lmax, n_seg)).astype(np.int64)
-    lens = np.maximum(lens, 1)
+    if lens is None:
+        lens = np.floor(2.0 ** rng.uniform(lmin, lmax, n_seg)).astype(np.int64)
+        lens = np.maximum(lens, 1)
+    else:
+        lens = np.asarray(lens, dtype=np.int64)
+        n_seg = len(lens)
     seg_off = np.zeros(n_seg + 1, dtype=np.int64)
     seg_off[1:] = np.cumsum(lens)
     qs = rng.uniform(*qrange, n_seg)
