@@ -77,19 +77,34 @@ MS_DEVONLY int64_t logical_block() {
 // needs (down to waiting for the previous state's stores).
 MS_DEVONLY void drain_vmem() { __builtin_amdgcn_s_waitcnt(0); }
 
+// Device-coherent (write-through) store: a relaxed agent-scope atomic store,
+// which bypasses keeping the line dirty in the XCD's L2.  Used for everything a
+// pass with a last-block tile scan writes before its blocks arrive: the
+// agent-scope release fence of the arrival writes back every dirty line of the
+// XCD's L2, and bulk outputs left dirty there made the last arrivals wait for
+// megabytes of write-back.
+template <typename P>
+MS_DEVONLY void wt_store(P* p, P v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// store: plain or write-through
+template <bool kWT, typename P>
+MS_DEVONLY void put(P* p, P v) {
+  if constexpr (kWT) wt_store(p, v); else *p = v;
+}
+
 template <int N> struct Sym { static constexpr int n = N * (N + 1) / 2; };
 template <int N> struct ElemSz { static constexpr int n = N * N + 2 * N + 2 * Sym<N>::n; };
 template <int N> struct AffSz { static constexpr int n = N * N + N + Sym<N>::n; };
 
 // --------------------------------------------------------------------------- SoA I/O
 // A "plane set" stores component c of item i at base[c * ld + i].
-template <typename T, int N>
+template <typename T, int N, bool kWT = false>
 MS_DEVONLY void store_sym(T* base, int64_t ld, int64_t i, const T (&a)[N][N], int c0 = 0) {
   int c = c0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int q = 0; q <= r; ++q) base[(c++) * ld + i] = a[r][q];
+    for (int q = 0; q <= r; ++q) put<kWT>(&base[(c++) * ld + i], a[r][q]);
 }
 template <typename T, int N>
 MS_DEVONLY void load_sym(const T* base, int64_t ld, int64_t i, T (&a)[N][N], int c0 = 0) {
@@ -102,22 +117,22 @@ MS_DEVONLY void load_sym(const T* base, int64_t ld, int64_t i, T (&a)[N][N], int
       a[q][r] = a[r][q];
     }
 }
-template <typename T, int N>
+template <typename T, int N, bool kWT = false>
 MS_DEVONLY void store_vec(T* base, int64_t ld, int64_t i, const T (&a)[N], int c0 = 0) {
 #pragma unroll
-  for (int r = 0; r < N; ++r) base[(c0 + r) * ld + i] = a[r];
+  for (int r = 0; r < N; ++r) put<kWT>(&base[(c0 + r) * ld + i], a[r]);
 }
 template <typename T, int N>
 MS_DEVONLY void load_vec(const T* base, int64_t ld, int64_t i, T (&a)[N], int c0 = 0) {
 #pragma unroll
   for (int r = 0; r < N; ++r) a[r] = base[(c0 + r) * ld + i];
 }
-template <typename T, int N, int M>
+template <typename T, int N, int M, bool kWT = false>
 MS_DEVONLY void store_mat(T* base, int64_t ld, int64_t i, const T (&a)[N][M], int c0 = 0) {
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int q = 0; q < M; ++q) base[(c0 + r * M + q) * ld + i] = a[r][q];
+    for (int q = 0; q < M; ++q) put<kWT>(&base[(c0 + r * M + q) * ld + i], a[r][q]);
 }
 template <typename T, int N, int M>
 MS_DEVONLY void load_mat(const T* base, int64_t ld, int64_t i, T (&a)[N][M], int c0 = 0) {
@@ -129,13 +144,13 @@ MS_DEVONLY void load_mat(const T* base, int64_t ld, int64_t i, T (&a)[N][M], int
 
 // tiled state-indexed I/O (C = components of the buffer, c0 = first one written)
 // (P = storage type of the buffer, T = compute type of the registers)
-template <typename P, typename T, int N>
+template <typename P, typename T, int N, bool kWT = false>
 MS_DEVONLY void tstore_sym(P* base, int C, int64_t i, const T (&a)[N][N], int c0 = 0) {
   int c = c0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int q = 0; q <= r; ++q) base[tix(i, c++, C)] = P(a[r][q]);
+    for (int q = 0; q <= r; ++q) put<kWT>(&base[tix(i, c++, C)], P(a[r][q]));
 }
 template <typename P, typename T, int N>
 MS_DEVONLY void tload_sym(const P* base, int C, int64_t i, T (&a)[N][N], int c0 = 0) {
@@ -148,10 +163,10 @@ MS_DEVONLY void tload_sym(const P* base, int C, int64_t i, T (&a)[N][N], int c0 
       a[q][r] = a[r][q];
     }
 }
-template <typename P, typename T, int N>
+template <typename P, typename T, int N, bool kWT = false>
 MS_DEVONLY void tstore_vec(P* base, int C, int64_t i, const T (&a)[N], int c0 = 0) {
 #pragma unroll
-  for (int r = 0; r < N; ++r) base[tix(i, c0 + r, C)] = P(a[r]);
+  for (int r = 0; r < N; ++r) put<kWT>(&base[tix(i, c0 + r, C)], P(a[r]));
 }
 template <typename P, typename T, int N>
 MS_DEVONLY void tload_vec(const P* base, int C, int64_t i, T (&a)[N], int c0 = 0) {
@@ -166,14 +181,96 @@ MS_DEVONLY void tstore_mat(P* base, int C, int64_t i, const T (&a)[N][M], int c0
     for (int q = 0; q < M; ++q) base[tix(i, c0 + r * M + q, C)] = P(a[r][q]);
 }
 
-// element planes: A (N*N), b (N), C (sym), eta (N), J (sym)
+// Per-lane workspace (the in-tile prefixes) is blocked by tile like the state
+// arrays: component c of lane g sits at ((g / 64) * C + c) * 64 + g % 64, so a
+// wavefront writes its own contiguous C * 512 bytes, one full 512-byte run per
+// component.  (Component-major planes over all lanes made every wavefront
+// write the same plane at the same moment.)
+struct LaneTiled {
+  int64_t C;  // components per lane
+  MS_DEV int64_t at(int64_t g, int64_t c) const { return ((g >> 6) * C + c) * kWave + (g & (kWave - 1)); }
+};
 template <typename T, int N>
+MS_DEVONLY void lt_store_elem(T* base, int64_t g, const Elem<T, N>& e) {
+  const LaneTiled L{ElemSz<N>::n};
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) wt_store(&base[L.at(g, c++)], e.A[r][q]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) wt_store(&base[L.at(g, c++)], e.b[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) wt_store(&base[L.at(g, c++)], e.C[r][q]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) wt_store(&base[L.at(g, c++)], e.eta[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) wt_store(&base[L.at(g, c++)], e.J[r][q]);
+}
+template <typename T, int N>
+MS_DEVONLY void lt_load_elem(const T* base, int64_t g, Elem<T, N>& e) {
+  const LaneTiled L{ElemSz<N>::n};
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) e.A[r][q] = base[L.at(g, c++)];
+#pragma unroll
+  for (int r = 0; r < N; ++r) e.b[r] = base[L.at(g, c++)];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { e.C[r][q] = base[L.at(g, c++)]; e.C[q][r] = e.C[r][q]; }
+#pragma unroll
+  for (int r = 0; r < N; ++r) e.eta[r] = base[L.at(g, c++)];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { e.J[r][q] = base[L.at(g, c++)]; e.J[q][r] = e.J[r][q]; }
+}
+template <typename T, int N>
+MS_DEVONLY void lt_store_aff(T* base, int64_t g, const Aff<T, N>& a) {
+  const LaneTiled L{AffSz<N>::n};
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) wt_store(&base[L.at(g, c++)], a.Phi[r][q]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) wt_store(&base[L.at(g, c++)], a.bt[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) wt_store(&base[L.at(g, c++)], a.Om[r][q]);
+}
+template <typename T, int N>
+MS_DEVONLY void lt_load_aff(const T* base, int64_t g, Aff<T, N>& a) {
+  const LaneTiled L{AffSz<N>::n};
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) a.Phi[r][q] = base[L.at(g, c++)];
+#pragma unroll
+  for (int r = 0; r < N; ++r) a.bt[r] = base[L.at(g, c++)];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { a.Om[r][q] = base[L.at(g, c++)]; a.Om[q][r] = a.Om[r][q]; }
+}
+
+// element planes: A (N*N), b (N), C (sym), eta (N), J (sym)
+template <typename T, int N, bool kWT = false>
 MS_DEVONLY void store_elem(T* base, int64_t ld, int64_t i, const Elem<T, N>& e) {
-  store_mat(base, ld, i, e.A, 0);
-  store_vec(base, ld, i, e.b, N * N);
-  store_sym(base, ld, i, e.C, N * N + N);
-  store_vec(base, ld, i, e.eta, N * N + N + Sym<N>::n);
-  store_sym(base, ld, i, e.J, N * N + 2 * N + Sym<N>::n);
+  store_mat<T, N, N, kWT>(base, ld, i, e.A, 0);
+  store_vec<T, N, kWT>(base, ld, i, e.b, N * N);
+  store_sym<T, N, kWT>(base, ld, i, e.C, N * N + N);
+  store_vec<T, N, kWT>(base, ld, i, e.eta, N * N + N + Sym<N>::n);
+  store_sym<T, N, kWT>(base, ld, i, e.J, N * N + 2 * N + Sym<N>::n);
 }
 template <typename T, int N>
 MS_DEVONLY void load_elem(const T* base, int64_t ld, int64_t i, Elem<T, N>& e) {
@@ -183,11 +280,11 @@ MS_DEVONLY void load_elem(const T* base, int64_t ld, int64_t i, Elem<T, N>& e) {
   load_vec(base, ld, i, e.eta, N * N + N + Sym<N>::n);
   load_sym(base, ld, i, e.J, N * N + 2 * N + Sym<N>::n);
 }
-template <typename T, int N>
+template <typename T, int N, bool kWT = false>
 MS_DEVONLY void store_aff(T* base, int64_t ld, int64_t i, const Aff<T, N>& a) {
-  store_mat(base, ld, i, a.Phi, 0);
-  store_vec(base, ld, i, a.bt, N * N);
-  store_sym(base, ld, i, a.Om, N * N + N);
+  store_mat<T, N, N, kWT>(base, ld, i, a.Phi, 0);
+  store_vec<T, N, kWT>(base, ld, i, a.bt, N * N);
+  store_sym<T, N, kWT>(base, ld, i, a.Om, N * N + N);
 }
 template <typename T, int N>
 MS_DEVONLY void load_aff(const T* base, int64_t ld, int64_t i, Aff<T, N>& a) {
@@ -215,11 +312,11 @@ MS_DEVONLY void shfl_aff(Aff<T, N>& o, const Aff<T, N>& a, int src) {
 // Pointers into the caller's workspace; sizes fixed by (n_states, L, N).
 template <typename T>
 struct Ws {
-  unsigned int* counters;  // [4], zero between launches
-  T* lane_pre;             // [ElemSz][n_lanes]   exclusive in-tile filter prefix per lane
+  unsigned int* counters;  // two sets of arrival counters (filter, trajectory), zero between launches
+  T* lane_pre;             // lane-tiled [ElemSz] per lane: exclusive in-tile filter prefix
   T* tile_agg;             // [ElemSz][n_tiles]
   T* tile_carry;           // [Sym + N][n_tiles]  (S, v) before each tile
-  T* slane_pre;            // [AffSz][n_lanes]    trajectory map from after the lane's chunk to tile end
+  T* slane_pre;            // lane-tiled [AffSz] per lane: trajectory map from after the lane's chunk to tile end
   T* stile_agg;            // [AffSz][n_tiles]
   T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
   int64_t n_lanes, n_tiles;
@@ -423,22 +520,58 @@ MS_DEVONLY void flush_lane(int64_t seg, double (&val)[K], double* const (&dst)[K
 }
 
 // --------------------------------------------------------------------------- last block
-MS_DEVONLY bool arrive_last(unsigned int* counter) {
+// Two-level arrival: a block first increments the counter of its group
+// (workgroup id mod 8, i.e. its XCD), and the last block of each group then
+// increments the top counter; the last of those is the last block overall.
+// Each device-scope atomic on one address is serialised at the memory side,
+// so 256 blocks on a single counter put ~20 us of queueing in front of the
+// last arrival; groups of 32 contend in parallel and only 8 reach the top.
+// counters[0..7]: groups, counters[8]: top.
+//
+// Ordering.  Everything the last block reads (the tile aggregates) is written
+// with device-coherent stores (wt_store: past the XCD's non-coherent L2), so a
+// block only has to wait for its own stores to complete before it counts
+// itself in; the last block then invalidates its L2 (agent-scope acquire)
+// before reading.  This is the protocol the compiler emits for agent-scope
+// release/acquire of atomic data; an agent-scope release fence would add an
+// L2 write-back (buffer_wbl2) per wavefront, which measured 10-30 us each here
+// and is only needed for ordinary (write-back) stores, of which the data read
+// across blocks has none.
+constexpr int kArriveGroups = 8;
+constexpr int kArriveWords = kArriveGroups + 1;
+constexpr int kCountersFilter = 0, kCountersTraj = 16;  // word offsets (64 words are cleared)
+
+MS_DEVONLY bool arrive_last(unsigned int* counters) {
   __shared__ unsigned int s_last;
-  __threadfence();
+  drain_vmem();  // this wavefront's device-coherent stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1) ? 1u : 0u;
+    const unsigned nb = gridDim.x, grp = blockIdx.x % kArriveGroups;
+    const unsigned gsize = nb / kArriveGroups + (grp < nb % kArriveGroups ? 1u : 0u);
+    const unsigned ngroups = nb < unsigned(kArriveGroups) ? nb : unsigned(kArriveGroups);
+    unsigned last = 0;
+    const unsigned t =
+        __hip_atomic_fetch_add(counters + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == gsize - 1) {
+      const unsigned u = __hip_atomic_fetch_add(counters + kArriveGroups, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      last = (u == ngroups - 1) ? 1u : 0u;
+    }
+    s_last = last;
   }
   __syncthreads();
   const bool last = s_last != 0;
-  if (last) __threadfence();
+  if (last) {
+    drain_vmem();  // the counter increment has returned
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   return last;
 }
 
-MS_DEVONLY void release_counter(unsigned int* counter) {
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Reset by the last block once every block has arrived.
+MS_DEVONLY void release_counter(unsigned int* counters) {
+  if (threadIdx.x < kArriveWords)
+    __hip_atomic_store(counters + threadIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Filter tile scan, run by the last block: (S, v) before every tile.
@@ -613,12 +746,29 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
 }
 
 // --------------------------------------------------------------------------- pass A
+// Zero the per-segment accumulators over the whole grid.  The filter
+// up-sweep does this for the passes that follow it (it runs before any of
+// them adds to the accumulators), which saves a launch.
+MS_DEVONLY void zero_acc_grid(const Acc& a, int64_t n_seg, int64_t nth) {
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  const int64_t t0 = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  for (int64_t i = t0; i < n_seg; i += stride) {
+    if (a.loglik) a.loglik[i] = 0.0;
+    if (a.obj) a.obj[i] = 0.0;
+  }
+  for (int64_t i = t0; i < n_seg * nth; i += stride) {
+    if (a.g_loglik) a.g_loglik[i] = 0.0;
+    if (a.g_obj) a.g_obj[i] = 0.0;
+  }
+}
+
 template <typename TS, typename T, class M, int L>
-__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws) {
+__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
+  zero_acc_grid(zacc, p.n_seg, M::NTH > 0 ? M::NTH : 1);
   const int64_t tile = g >> 6;
   const int64_t j0 = g * L;
   const int64_t j1 = lane_end(g, ws.n_lanes, p.n_states);
@@ -665,11 +815,15 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws) {
   }
   shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
   if (lane == 0) elem_identity(o);
-  if (g < ws.n_lanes) store_elem(ws.lane_pre, ws.n_lanes, g, o);
-  if (lane == kWave - 1 && tile < ws.n_tiles) store_elem(ws.tile_agg, ws.n_tiles, tile, agg);
-  if (arrive_last(ws.counters + 0)) {
+  if (lane == kWave - 1 && tile < ws.n_tiles) store_elem<T, N, true>(ws.tile_agg, ws.n_tiles, tile, agg);
+  const bool last = arrive_last(ws.counters + kCountersFilter);
+  // The lane prefixes are read only by the next kernel, so they are written
+  // after the arrival: the release fence does not wait for them, and they
+  // drain while the last block scans the tiles.
+  if (g < ws.n_lanes) lt_store_elem(ws.lane_pre, g, o);
+  if (last) {
     filter_tile_scan<T, N>(ws);
-    release_counter(ws.counters + 0);
+    release_counter(ws.counters + kCountersFilter);
   }
 }
 
@@ -746,7 +900,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
       load_sym(ws.tile_carry, ws.n_tiles, tile, S, 0);
       load_vec(ws.tile_carry, ws.n_tiles, tile, v, Sym<N>::n);
       Elem<T, N> lp;
-      load_elem(ws.lane_pre, ws.n_lanes, g, lp);
+      lt_load_elem(ws.lane_pre, g, lp);
       carry_apply(S, v, lp);
     }
   }
@@ -815,8 +969,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
 #pragma unroll
           for (int r = 0; r < N; ++r) v[r] = vn[r];
         }
-        tstore_sym(So, Sym<N>::n, i, S);
-        tstore_vec(vo, N, i, v);
+        tstore_sym<TS, T, N, kTraj>(So, Sym<N>::n, i, S);
+        tstore_vec<TS, T, N, kTraj>(vo, N, i, v);
         if (kMode == kModeFilter && mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
@@ -889,11 +1043,13 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
     }
     shfl_aff(o, sagg, lane + 1 < kWave ? lane + 1 : lane);
     if (lane == kWave - 1) aff_identity(o);
-    if (g < ws.n_lanes) store_aff(ws.slane_pre, ws.n_lanes, g, o);
-    if (lane == 0 && tile < ws.n_tiles) store_aff(ws.stile_agg, ws.n_tiles, tile, sagg);
-    if (arrive_last(ws.counters + 1)) {
+    if (lane == 0 && tile < ws.n_tiles) store_aff<T, N, true>(ws.stile_agg, ws.n_tiles, tile, sagg);
+    const bool last = arrive_last(ws.counters + kCountersTraj);
+    // read only by the next kernel: written after the arrival (see the filter up-sweep)
+    if (g < ws.n_lanes) lt_store_aff(ws.slane_pre, g, o);
+    if (last) {
       traj_tile_scan<T, N>(ws);
-      release_counter(ws.counters + 1);
+      release_counter(ws.counters + kCountersTraj);
     }
   }
 }
@@ -927,7 +1083,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     load_vec(ws.stile_carry, ws.n_tiles, tile, x, 0);
     load_sym(ws.stile_carry, ws.n_tiles, tile, P, N);
     Aff<T, N> lp;
-    load_aff(ws.slane_pre, ws.n_lanes, g, lp);
+    lt_load_aff(ws.slane_pre, g, lp);
     aff_apply(lp, x, P);
   }
   double val[KV];
@@ -1202,15 +1358,7 @@ __global__ void __launch_bounds__(kBlock) k_build_elements(Prob<TS> p, TS* out) 
 
 // Zero the per-segment accumulators that a pass adds into atomically.
 static __global__ void __launch_bounds__(kBlock) k_zero_acc(Acc a, int64_t n_seg, int64_t nth) {
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_seg; i += stride) {
-    if (a.loglik) a.loglik[i] = 0.0;
-    if (a.obj) a.obj[i] = 0.0;
-  }
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_seg * nth; i += stride) {
-    if (a.g_loglik) a.g_loglik[i] = 0.0;
-    if (a.g_obj) a.g_obj[i] = 0.0;
-  }
+  zero_acc_grid(a, n_seg, nth);
 }
 
 }  // namespace ms

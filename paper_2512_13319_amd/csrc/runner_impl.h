@@ -133,10 +133,9 @@ template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
-  MS_CHECK(zero(Acc{a.loglik, nullptr, nullptr, nullptr}, q.n_seg, M::NTH, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
@@ -169,13 +168,11 @@ template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
-  const int64_t nth = M::NTH;
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
-  MS_CHECK(zero(Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
-                q.n_seg, nth, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w);
+  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(
+      p, w, Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
