@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6144)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default schedule instead of autotuning it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -113,6 +115,8 @@ def main():
     wl = workloads.cv(T=T, d=2, dt=1e-3, q=0.5, r=0.05, m0=[5, 5, 0, 0], P0=1e-2 * np.eye(4),
                       seed=2, name="cfg2_cv2d")
     p = ms.problem_from_workload(wl, dtype=tdt, device=dev)
+    # schedule (states per lane) picked by the library's autotuner, untimed
+    chunk = None if args.no_autotune else ms.autotune(p)
     nsym = p.nsym
     out = dict(S=p._tiled(nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx), Ps=p._tiled(nsym),
                loglik=p._empty(1, dtype=torch.float64), obj=p._empty(1, dtype=torch.float64),
@@ -213,7 +217,8 @@ def main():
         "config": {"workload": "2-D constant-velocity SDE nx=4 ny=2, T=2^%d steps dt=1e-3, q=0.5, "
                                "r=0.05, one trajectory; filter + smoother (x*, P^s) + log-lik + "
                                "objective + adjoint d/d(gamma,q,r)" % args.log2T,
-                   "T": T, "nx": 4, "ny": 2, "n_seg": 1, "storage": args.dtype},
+                   "T": T, "nx": 4, "ny": 2, "n_seg": 1, "storage": args.dtype,
+                   "schedule": {"states_per_lane": chunk, "autotuned": chunk is not None}},
         "plain_scan": {"value": T / (ms_pl * 1e-3), "ms_per_step": ms_pl,
                        "kernels_ms": {k: round(v[1], 4) for k, v in kern_pl.items()}},
         "wall_ms_per_step": round(wall_fa, 4),

@@ -26,8 +26,9 @@
  *    per-segment scalar outputs (log-likelihood, objective, gradients) are
  *    always double.
  *  - Every array pointer is a DEVICE pointer owned by the caller, except
- *    seg_off_host.  Nothing is allocated or freed by the library; the
- *    workspace is caller-owned too (map_workspace_bytes, map_workspace_init).
+ *    seg_off_host.  Nothing is allocated or freed by the library (except
+ *    map_autotune's temporary outputs); the workspace is caller-owned too
+ *    (map_workspace_bytes, map_workspace_init).
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
  *    void*, NULL = the default stream).  A call returns after enqueueing.
  *  - Steps of all segments are concatenated: segment s owns steps
@@ -35,13 +36,15 @@
  *    (T_s steps give T_s+1 states; state seg_off[s]+s is the prior time t0).
  *    n_states = n_steps + n_seg.  Step k of segment s ends at state k + s + 1.
  *  - State-indexed arrays use the TILED layout (MAPSCAN_TILE = 1024 states
- *    per tile, matching the kernels' work unit of 64 lanes x 16 consecutive
- *    states).  For an array with C components, component c of state i is at
+ *    per tile: 16 rows of 64 states).  For an array with C components,
+ *    component c of state i is at
  *        ((i / 1024) * C + c) * 1024 + (i % 16) * 64 + (i / 16) % 64,
  *    and the buffer holds ceil(n_states / 1024) * C * 1024 elements (the
  *    caller allocates the padding; padded entries are never read as data and
- *    may be written).  This makes every access of a wavefront a contiguous
- *    run.  Measurements y and per-step lengths dt are given per state too:
+ *    may be written).  The kernels give each lane `chunk` consecutive states
+ *    (a schedule: 4, 8 or 16, see map_problem.chunk), so every access of a
+ *    wavefront covers whole cache lines.  Measurements y and per-step lengths
+ *    dt are given per state too:
  *    the value of the step that ends at state i (entries at a segment's first
  *    state are ignored).
  *  - Symmetric nx x nx matrices are nx(nx+1)/2 components, lower triangle in
@@ -62,7 +65,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 2
+#define MAPSCAN_ABI_VERSION 3
 #define MAPSCAN_TILE 1024
 
 typedef enum {
@@ -128,10 +131,17 @@ typedef struct {
    * step k at base + k * stride (stride 0: one matrix for all steps). */
   const void *F, *c, *L, *W, *H, *r, *R;
   int64_t F_stride, c_stride, L_stride, W_stride, H_stride, r_stride, R_stride;
+  /* Schedule: states per lane (4, 8 or 16), or 0 to let the library choose:
+   * the choice map_autotune recorded for this problem's shape, else the
+   * largest chunk that still gives every second SIMD of the device a
+   * wavefront.
+   * Results do not depend on it beyond rounding. */
+  int32_t chunk;
 } map_problem;
 
 /* Size in bytes of the workspace every scan entry needs for this problem
- * (0 if the problem is invalid; see map_last_error). */
+ * (0 if the problem is invalid; see map_last_error).  With chunk = 0 it fits
+ * every schedule the library may choose. */
 size_t map_workspace_bytes(const map_problem* p);
 
 /* Zero the workspace's control words.  Call once after allocating a
@@ -193,6 +203,20 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* Schedule autotuner for the batched segmented scan (spec item: tile
+ * size per problem shape).  Times the fused step (map_smooth with every
+ * output, gradients for parametric models) at chunk = 16, 8 and 4 on the
+ * caller's inputs (p->chunk is ignored; p->xbar must be set for nonlinear
+ * models) and records the fastest for this shape -- model, dimensions,
+ * dtype, floor(log2 n_states), floor(log2 n_seg) -- so that later calls with
+ * chunk = 0 use it.  ws: a workspace of map_workspace_bytes(p with chunk 0)
+ * bytes, initialised.  cache_path (host string or NULL): a text file of
+ * "key chunk ms" lines read first (a recorded shape is not timed again) and
+ * appended to.  Allocates and frees its temporary outputs; synchronises
+ * `stream`.  *chunk_out receives the chosen chunk. */
+map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,
+                        int32_t* chunk_out, void* stream);
 
 /* Measurement hook (no effect on results).  map_profile_enable(n) creates n
  * pairs of HIP events (0 disables and releases them); while enabled, each

@@ -17,6 +17,7 @@ lower-triangle components.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -105,11 +106,15 @@ class Problem:
     dtype     storage precision of every array (torch.float64 or torch.float32)
     arith     arithmetic precision: "f64" (default; with float32 storage this is
               the accurate FP32 mode) or "f32" (float32 storage only)
+    chunk     schedule: states per lane (4, 8, 16) or 0 for the library's choice
+              (an autotuned one for this shape if `autotune` ran, else a
+              heuristic)
     """
 
     def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
-                 dtype=torch.float64, device="cuda", arith="f64"):
+                 dtype=torch.float64, device="cuda", arith="f64", chunk=0):
         _lib.load()
+        self.chunk = int(chunk)
         self.model, self.nx, self.ny, self.nw = model, nx, ny, nw
         self.dtype, self.device = dtype, torch.device(device)
         if arith not in ("f64", "f32") or (arith == "f32" and dtype != torch.float32):
@@ -158,6 +163,7 @@ class Problem:
         s.model = MODELS[self.model]
         s.n_theta = self.n_theta
         s.n_seg, s.n_steps = self.n_seg, self.n_steps
+        s.chunk = self.chunk
         s.seg_off = self.seg_off.data_ptr()
         s.seg_off_host = self.seg_off_host.ctypes.data
         s.dt = self.dt.data_ptr()
@@ -223,11 +229,29 @@ def _nat(p, r, natural):
             for k, v in r.items()}
 
 
-def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, arith="f64"):
+def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, arith="f64",
+                          chunk=0):
     """Device-resident Problem from a `workloads.Workload`-like object."""
     return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
                    theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
-                   lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith)
+                   lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith,
+                   chunk=chunk)
+
+
+def autotune(p: Problem, cache_path=None) -> int:
+    """Time the fused step at every schedule (states per lane) on this problem
+    and record the fastest for its shape; later calls with chunk = 0 use it.
+    A nonlinear problem needs its linearisation point set (`set_xbar`).
+    Returns the chosen chunk.  Synchronises the current stream."""
+    lib = _lib.load()
+    if p.chunk != 0:
+        raise ValueError("autotune needs a Problem with chunk=0")
+    ws = p.workspace()
+    out = ctypes.c_int32(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _lib.check(lib.map_autotune(ctypes.byref(p.struct), _ptr(ws), ws.numel(), path,
+                                ctypes.byref(out), _stream()))
+    return int(out.value)
 
 
 def build_elements(p: Problem, natural=True):

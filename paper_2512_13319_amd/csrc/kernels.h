@@ -33,28 +33,32 @@ namespace ms {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
-constexpr int kChunk = 16;                   // states per lane
-constexpr int64_t kTile = kWave * kChunk;    // states per wavefront tile
+constexpr int kRow = 16;                     // storage: states per row of a tile
+constexpr int64_t kTile = kWave * kRow;      // storage: states per tile
 
-// Tiled layout of every state-indexed array with C components: tile
+// Tiled storage layout of every state-indexed array with C components: tile
 // (i / 1024) holds C blocks of 1024 values; inside a block, value of state i
-// sits at (i % 16) * 64 + (i / 16) % 64.  Iteration t of a wavefront (lane l
-// owns states 16 l .. 16 l + 15 of its tile) then touches 64 consecutive
-// addresses per component.
+// sits at (i % 16) * 64 + (i / 16) % 64.
+//
+// Work decomposition: lane g runs `chunk` consecutive states (chunk = 4, 8 or
+// 16, a schedule parameter); 64 lanes form a work tile of 64 * chunk states.
+// Iteration t of a wavefront then touches, per component, 64 / (16 / chunk)
+// consecutive values in each of 16 / chunk rows: whole 128-byte lines (FP64)
+// in every case, one 512-byte run at chunk 16.
 MS_DEV int64_t tix(int64_t i, int64_t c, int64_t C) {
-  return ((i >> 10) * C + c) * kTile + ((i & (kChunk - 1)) << 6) + ((i >> 4) & (kWave - 1));
+  return ((i >> 10) * C + c) * kTile + ((i & (kRow - 1)) << 6) + ((i >> 4) & (kWave - 1));
 }
 
-// One past the last state of lane g, whose states start at 16 g: lane g runs
-// states 16 g .. 16 g + 15, the sequence's last work lane also runs whatever
-// follows (a short final tile merged into the work tile before it; n_lanes
-// counts work lanes), and a lane past the work lanes runs none (its range is
-// empty even where 16 g < n_states, i.e. in a merged final tile).
-MS_DEV int64_t lane_end(int64_t g, int64_t n_lanes, int64_t n_states) {
-  const int64_t j0 = g * kChunk;
+// One past the last state of lane g, whose states start at chunk * g: lane g
+// runs chunk states, the sequence's last work lane also runs whatever follows
+// (a short final work tile merged into the one before it; n_lanes counts work
+// lanes), and a lane past the work lanes runs none (its range is empty even
+// where chunk * g < n_states, i.e. in a merged final tile).
+MS_DEV int64_t lane_end(int64_t g, int64_t n_lanes, int64_t n_states, int64_t chunk) {
+  const int64_t j0 = g * chunk;
   if (g >= n_lanes || j0 >= n_states) return j0;
   if (g == n_lanes - 1) return n_states;
-  return j0 + kChunk < n_states ? j0 + kChunk : n_states;
+  return j0 + chunk < n_states ? j0 + chunk : n_states;
 }
 
 // Logical block of this workgroup.  Workgroups are dispatched to the eight
@@ -320,6 +324,7 @@ struct Ws {
   T* stile_agg;            // [AffSz][n_tiles]
   T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
   int64_t n_lanes, n_tiles;
+  int64_t chunk;           // states per lane
 };
 
 // Per-segment accumulators (double): loglik [n_seg], obj [n_seg],
@@ -762,16 +767,15 @@ MS_DEVONLY void zero_acc_grid(const Acc& a, int64_t n_seg, int64_t nth) {
   }
 }
 
-template <typename TS, typename T, class M, int L>
+template <typename TS, typename T, class M>
 __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
-  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   zero_acc_grid(zacc, p.n_seg, M::NTH > 0 ? M::NTH : 1);
   const int64_t tile = g >> 6;
-  const int64_t j0 = g * L;
-  const int64_t j1 = lane_end(g, ws.n_lanes, p.n_states);
+  const int64_t j0 = g * ws.chunk;
+  const int64_t j1 = lane_end(g, ws.n_lanes, p.n_states, ws.chunk);
   Elem<T, N> agg;
   elem_identity(agg);
   if (j0 < j1) {
@@ -878,18 +882,17 @@ MS_DEVONLY double pred_loglik(const T (&Sp)[N][N], const T (&vp)[N], const Step<
   return -0.5 * (double(NY) * 1.8378770664093453 + 2.0 * ::log(det) + q);
 }
 
-template <typename TS, typename T, class M, int L, int kMode>
+template <typename TS, typename T, class M, int kMode>
 __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, FilterOut fo, Acc acc) {
-  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr bool kFilter = kMode != kModeTrajOnly;
   constexpr bool kTraj = kMode != kModeFilter;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
-  const int64_t j0 = g * L;
+  const int64_t j0 = g * ws.chunk;
   const int64_t ns = p.n_states;
-  const int64_t j1 = lane_end(g, ws.n_lanes, ns);
+  const int64_t j1 = lane_end(g, ws.n_lanes, ns, ws.chunk);
   TS* So = static_cast<TS*>(fo.S);
   TS* vo = static_cast<TS*>(fo.v);
   TS* mo = static_cast<TS*>(fo.m);
@@ -1064,15 +1067,14 @@ struct TrajOut {
   int want_grad;
 };
 
-template <typename TS, typename T, class M, int L, bool kGrad, bool kCov>
+template <typename TS, typename T, class M, bool kGrad, bool kCov>
 __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, TrajOut to, Acc acc) {
-  static_assert(L == kChunk, "the tiled state layout fixes 16 states per lane");
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
   constexpr int KV = 1 + 2 * NTH;
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
-  const int64_t j0 = g * L;
+  const int64_t j0 = g * ws.chunk;
   const int64_t ns = p.n_states;
   const TS* Si = static_cast<const TS*>(to.S);
   const TS* vi = static_cast<const TS*>(to.v);
@@ -1100,7 +1102,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     dstr[1 + t] = dstr[1 + NTH + t] = NTH;
   }
   int64_t seg_acc = -1;
-  const int64_t j1 = lane_end(g, ws.n_lanes, ns);
+  const int64_t j1 = lane_end(g, ws.n_lanes, ns, ws.chunk);
   if (j0 < j1) {
     const int64_t il = j1 - 1;
     Cursor<TS, T, M> cur;

@@ -1,8 +1,12 @@
-// C-ABI front end: host-side validation, dispatch to the (dtype, model)
-// instantiation, error reporting.  Nothing here allocates device memory.
+// C-ABI front end: host-side validation, schedule choice, dispatch to the
+// (dtype, model) instantiation, error reporting.  Only map_autotune allocates
+// device memory (temporary outputs, freed before it returns).
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +124,8 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
     return fail(MAP_E_DIM, "dimensions (nx, ny, nw) = (%d, %d, %d) outside [1, 8]", p.nx, p.ny, p.nw);
   if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_LORENZ63)
     return fail(MAP_E_ARG, "unknown model %d", p.model);
+  if (p.chunk != 0 && !valid_chunk(p.chunk))
+    return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8 or 16", p.chunk);
   const int nth = model_ntheta(p);
   if (nth < 0)
     return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
@@ -163,8 +169,68 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
 size_t compute_bytes(int dtype) { return dtype == MAP_F32_FAST ? 4 : 8; }
 size_t storage_bytes(int dtype) { return dtype == MAP_F64 ? 8 : 4; }
 
+// ---------------------------------------------------------------- schedules
+// The schedule is the number of states per lane (4, 8 or 16).  Choices made
+// by map_autotune are kept per problem shape (model, dimensions, dtype, and
+// the powers of two of the state and segment counts); otherwise the largest
+// chunk that still gives at least one wavefront to every second SIMD (fewer
+// states per lane shorten each lane's chain but add wavefront-scan levels
+// per state: at 2^18 + 1 states, 8 per lane on half the SIMDs measured faster
+// than 4 per lane on all of them).
+namespace sched {
+static std::mutex g_mu;
+static std::map<std::string, int> g_tuned;
+static std::map<int, int> g_simds;  // device -> SIMD count
+
+std::string key_of(const map_problem& p) {
+  const int64_t ns = p.n_steps + p.n_seg;
+  char buf[128];
+  snprintf(buf, sizeof(buf), "m%d_x%d_y%d_w%d_d%d_s%d_g%d", p.model, p.nx, p.ny, p.nw, p.dtype,
+           int(floor(log2(double(ns)))), int(floor(log2(double(p.n_seg)))));
+  return buf;
+}
+
+int simds() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_simds.find(dev);
+  if (it != g_simds.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  return g_simds[dev] = 4 * cus;
+}
+
+int heuristic(const map_problem& p) {
+  const int64_t ns = p.n_steps + p.n_seg;
+  const int64_t want = simds() / 2;
+  for (int c : kChunks)
+    if (work_tiles(ns, c) >= want) return c;
+  return kChunks[2];
+}
+
+int resolve(const map_problem& p) {
+  if (p.chunk != 0) return p.chunk;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tuned.find(key_of(p));
+    if (it != g_tuned.end()) return it->second;
+  }
+  return heuristic(p);
+}
+
+// workspace that fits the schedule `resolve` may pick (the smallest chunk when
+// the choice is left to the library)
+size_t ws_bytes_for(const map_problem& p) {
+  const int c = p.chunk != 0 ? p.chunk : kChunks[2];
+  return ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), c).total;
+}
+}  // namespace sched
+
 map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
-  const size_t need = ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype)).total;
+  const size_t need =
+      ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), sched::resolve(p)).total;
   if (ws == nullptr) return fail(MAP_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < need)
     return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -219,7 +285,7 @@ extern "C" {
 
 size_t map_workspace_bytes(const map_problem* p) {
   if (validate(p, false) != MAP_OK) return 0;
-  return ws_layout(p->nx, p->n_steps + p->n_seg, compute_bytes(p->dtype)).total;
+  return sched::ws_bytes_for(*p);
 }
 
 map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream) {
@@ -243,7 +309,7 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
   if ((m == nullptr) != (P == nullptr)) return fail(MAP_E_ARG, "m and P must be given together");
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
-               static_cast<hipStream_t>(stream)};
+               static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return dispatch(*p, DoFilter{*p, a});
 }
 
@@ -254,7 +320,7 @@ map_status map_smoother_scan(const map_problem* p, const void* S, const void* v,
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               nullptr, nullptr, ws, static_cast<hipStream_t>(stream)};
+               nullptr, nullptr, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return dispatch(*p, DoSmoother{*p, a, false});
 }
 
@@ -268,7 +334,7 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
-               static_cast<hipStream_t>(stream)};
+               static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return dispatch(*p, DoSmooth{*p, a});
 }
 
@@ -307,7 +373,7 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
     q.xbar = bufs[cur];
     SmoothArgs a{S, v, nullptr, nullptr, bufs[1 - cur], last ? Ps : nullptr,
                  last ? loglik : nullptr, last ? obj : nullptr, last ? g_loglik : nullptr,
-                 last ? g_obj : nullptr, ws, st};
+                 last ? g_obj : nullptr, ws, st, sched::resolve(q)};
     s = dispatch(q, DoSmooth{q, a});
     if (s != MAP_OK) return s;
     cur = 1 - cur;
@@ -325,8 +391,105 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               g_loglik, g_obj, ws, static_cast<hipStream_t>(stream)};
+               g_loglik, g_obj, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return dispatch(*p, DoSmoother{*p, a, true});
+}
+
+map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,
+                        int32_t* chunk_out, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (chunk_out == nullptr) return fail(MAP_E_ARG, "chunk_out is NULL");
+  map_problem q = *p;
+  q.chunk = 0;
+  if (ws == nullptr || ws_bytes < sched::ws_bytes_for(q))
+    return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,
+                sched::ws_bytes_for(q));
+  const std::string key = sched::key_of(q);
+  if (cache_path != nullptr) {
+    if (FILE* fh = fopen(cache_path, "r")) {
+      char k[128];
+      int c = 0;
+      double t = 0.0;
+      std::lock_guard<std::mutex> lk(sched::g_mu);
+      while (fscanf(fh, "%127s %d %lf", k, &c, &t) == 3)
+        if (valid_chunk(c)) sched::g_tuned[k] = c;
+      fclose(fh);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(sched::g_mu);
+    auto it = sched::g_tuned.find(key);
+    if (it != sched::g_tuned.end()) {
+      *chunk_out = it->second;
+      return MAP_OK;
+    }
+  }
+  // temporary outputs for timing the fused step (the work map_smooth does
+  // with every output requested)
+  const int64_t ns = q.n_steps + q.n_seg;
+  const size_t tiled = size_t((ns + 1023) / 1024) * 1024 * storage_bytes(q.dtype);
+  const int nsym = q.nx * (q.nx + 1) / 2;
+  const int nth = model_ntheta(q);
+  const size_t sizes[8] = {tiled * nsym, tiled * q.nx, tiled * q.nx, tiled * nsym,
+                           size_t(q.n_seg) * 8, size_t(q.n_seg) * 8,
+                           nth > 0 ? size_t(q.n_seg) * nth * 8 : 0, nth > 0 ? size_t(q.n_seg) * nth * 8 : 0};
+  void* buf[8] = {};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto cleanup = [&]() {
+    for (void*& b : buf)
+      if (b) { hipFree(b); b = nullptr; }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  for (int i = 0; i < 8; ++i)
+    if (sizes[i] && hipMalloc(&buf[i], sizes[i]) != hipSuccess) {
+      cleanup();
+      return fail(MAP_E_HIP, "map_autotune: hipMalloc of %zu bytes failed", sizes[i]);
+    }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(MAP_E_HIP, "map_autotune: hipEventCreate failed");
+  }
+  int best = 0;
+  float best_ms = 0.f;
+  constexpr int kReps = 3;
+  for (int c : kChunks) {
+    q.chunk = c;
+    SmoothArgs a{buf[0], buf[1], nullptr, nullptr, buf[2], buf[3], static_cast<double*>(buf[4]),
+                 static_cast<double*>(buf[5]), static_cast<double*>(buf[6]),
+                 static_cast<double*>(buf[7]), ws, st, c};
+    s = dispatch(q, DoSmooth{q, a});  // warm-up
+    if (s == MAP_OK) s = hip_status(hipEventRecord(e0, st), "map_autotune");
+    for (int r = 0; r < kReps && s == MAP_OK; ++r) s = dispatch(q, DoSmooth{q, a});
+    if (s == MAP_OK) s = hip_status(hipEventRecord(e1, st), "map_autotune");
+    if (s == MAP_OK) s = hip_status(hipEventSynchronize(e1), "map_autotune");
+    float ms = 0.f;
+    if (s == MAP_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "map_autotune");
+    if (s != MAP_OK) {
+      cleanup();
+      return s;
+    }
+    ms /= kReps;
+    if (best == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  cleanup();
+  {
+    std::lock_guard<std::mutex> lk(sched::g_mu);
+    sched::g_tuned[key] = best;
+  }
+  if (cache_path != nullptr) {
+    if (FILE* fh = fopen(cache_path, "a")) {
+      fprintf(fh, "%s %d %.6f\n", key.c_str(), best, double(best_ms));
+      fclose(fh);
+    }
+  }
+  *chunk_out = best;
+  return MAP_OK;
 }
 
 map_status map_profile_enable(int32_t capacity) {

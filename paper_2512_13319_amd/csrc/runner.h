@@ -17,23 +17,27 @@ struct WsLayout {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Work tiles (1024 states, one per wavefront).  A final tile of at most
-// kMergeStates states is not given a wavefront of its own: the last lane of the
-// tile before it runs those states after its own 16 (a grid of 2^k steps has
-// 2^k + 1 states, and a one-state tile would otherwise make a block that can
-// only start once an earlier block has left its compute unit).  The storage
-// layout of state-indexed arrays does not depend on this.
+// Work tiles: 64 lanes of `chunk` states (chunk = 4, 8 or 16), one per
+// wavefront.  A final work tile of at most kMergeStates states is not given a
+// wavefront of its own: the last lane of the tile before it runs those states
+// after its own (a grid of 2^k steps has 2^k + 1 states, and a one-state tile
+// would otherwise make a block that can only start once an earlier block has
+// left its compute unit).  The storage layout of state-indexed arrays does
+// not depend on this.
 constexpr int64_t kMergeStates = 8;
-inline int64_t work_tiles(int64_t n_states) {
-  constexpr int64_t kTileStates = 1024;
-  const int64_t full = n_states / kTileStates, rem = n_states % kTileStates;
+constexpr int kChunks[3] = {16, 8, 4};  // schedules, largest first
+inline bool valid_chunk(int c) { return c == 4 || c == 8 || c == 16; }
+
+inline int64_t work_tiles(int64_t n_states, int64_t chunk) {
+  const int64_t ts = 64 * chunk;
+  const int64_t full = n_states / ts, rem = n_states % ts;
   if (full > 0 && rem > 0 && rem <= kMergeStates) return full;
-  return (n_states + kTileStates - 1) / kTileStates;
+  return (n_states + ts - 1) / ts;
 }
 
-inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz) {
+inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   WsLayout w;
-  w.n_tiles = work_tiles(n_states);
+  w.n_tiles = work_tiles(n_states, chunk);
   w.n_lanes = w.n_tiles * 64;
   const int64_t sym = nx * (nx + 1) / 2;
   const int64_t elem = nx * nx + 2 * nx + 2 * sym;
@@ -67,6 +71,7 @@ struct SmoothArgs {
   double* g_obj;
   void* ws;
   hipStream_t stream;
+  int chunk;  // states per lane (4, 8 or 16)
 };
 
 // Profiling hook: kernel kinds timed by HIP events when enabled.

@@ -40,8 +40,8 @@ inline Prob<T> make_prob(const map_problem& q) {
 }
 
 template <typename T>
-inline Ws<T> make_ws(int nx, int64_t n_states, void* base) {
-  WsLayout l = ws_layout(nx, n_states, sizeof(T));
+inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk) {
+  WsLayout l = ws_layout(nx, n_states, sizeof(T), chunk);
   char* b = static_cast<char*>(base);
   Ws<T> w;
   w.counters = reinterpret_cast<unsigned int*>(b + l.off[0]);
@@ -53,6 +53,7 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base) {
   w.stile_carry = reinterpret_cast<T*>(b + l.off[6]);
   w.n_lanes = l.n_lanes;
   w.n_tiles = l.n_tiles;
+  w.chunk = chunk;
   return w;
 }
 
@@ -112,9 +113,9 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
     if (grad) {
       prof_begin(kProfTrajDownGrad, st);
       if (cov)
-        k_traj_down<TS, T, M, kChunk, true, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+        k_traj_down<TS, T, M, true, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
       else
-        k_traj_down<TS, T, M, kChunk, true, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+        k_traj_down<TS, T, M, true, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
       prof_end(kProfTrajDownGrad, st);
       return hipGetLastError();
     }
@@ -122,9 +123,9 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
   to.want_grad = 0;
   prof_begin(kProfTrajDown, st);
   if (cov)
-    k_traj_down<TS, T, M, kChunk, false, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+    k_traj_down<TS, T, M, false, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
   else
-    k_traj_down<TS, T, M, kChunk, false, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+    k_traj_down<TS, T, M, false, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
   prof_end(kProfTrajDown, st);
   return hipGetLastError();
 }
@@ -132,16 +133,16 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
+  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
   Acc acc{a.loglik, nullptr, nullptr, nullptr};
   prof_begin(kProfFilterDown, a.stream);
-  k_filter_down<TS, T, M, kChunk, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kModeFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfFilterDown, a.stream);
   return hipGetLastError();
 }
@@ -149,7 +150,7 @@ hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a, bool grad) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
   const int64_t nth = M::NTH;
   MS_CHECK(zero(Acc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
                 q.n_seg, nth, a.stream));
@@ -157,7 +158,7 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
   FilterOut fo{a.S, a.v, nullptr, nullptr, 0};
   Acc acc{nullptr, a.obj, a.g_loglik, a.g_obj};
   prof_begin(kProfTrajUp, a.stream);
-  k_filter_down<TS, T, M, kChunk, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfTrajUp, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
@@ -167,18 +168,18 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M, kChunk><<<g, kBlock, 0, a.stream>>>(
+  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(
       p, w, Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
   Acc acc{a.loglik, a.obj, a.g_loglik, a.g_obj};
   prof_begin(kProfFused, a.stream);
-  k_filter_down<TS, T, M, kChunk, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  k_filter_down<TS, T, M, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfFused, a.stream);
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};

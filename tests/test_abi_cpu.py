@@ -85,6 +85,36 @@ def test_workspace_bytes(seg):
     assert b"outside" in lib.map_last_error()
 
 
+def test_workspace_bytes_by_schedule(seg):
+    """The workspace shrinks with more states per lane; chunk 0 (the library's
+    choice) fits every schedule; other values are rejected."""
+    lib = _lib.load()
+    big = np.array([0, 5000, 12000], dtype=np.int64)   # 12002 states: 12, 24, 47 work tiles
+    sizes = {}
+    for c in (0, 4, 8, 16):
+        p = good(big)
+        p.chunk = c
+        sizes[c] = lib.map_workspace_bytes(ctypes.byref(p))
+    assert sizes[16] < sizes[8] < sizes[4] == sizes[0]
+    p = good(seg)
+    p.chunk = 5
+    assert lib.map_workspace_bytes(ctypes.byref(p)) == 0
+    assert b"chunk" in lib.map_last_error()
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+
+
+def test_autotune_validates_before_running(seg):
+    lib = _lib.load()
+    out = ctypes.c_int32(0)
+    p = good(seg)
+    assert lib.map_autotune(ctypes.byref(p), FAKE, 1 << 40, None, None, None) == -1
+    assert lib.map_autotune(ctypes.byref(p), None, 1 << 40, None, ctypes.byref(out), None) == -7
+    assert lib.map_autotune(ctypes.byref(p), FAKE, 16, None, ctypes.byref(out), None) == -7
+    p.dtype = 9
+    assert lib.map_autotune(ctypes.byref(p), FAKE, 1 << 40, None, ctypes.byref(out), None) == -3
+
+
 @pytest.mark.parametrize("mutate,expect", [
     (lambda p: setattr(p, "dtype", 7), -3),
     (lambda p: setattr(p, "nx", 0), -2),

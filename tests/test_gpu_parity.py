@@ -74,10 +74,22 @@ CASES = {
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_linear_smoother_parity(case, dtype):
+    # chunk 0: the library's choice (4 states per lane at these sizes)
+    _check_linear(case, dtype, 0)
+
+
+@pytest.mark.parametrize("chunk", [8, 16])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_linear_smoother_parity_schedules(case, chunk):
+    """The other work decompositions (8 and 16 states per lane)."""
+    _check_linear(case, "f64", chunk)
+
+
+def _check_linear(case, dtype, chunk):
     ms = _mapscan()
     wl = CASES[case]().rounded(dtype)
     o = _oracle(wl)
-    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype], chunk=chunk)
     r = ms.smooth(p, covariances=True, loglik=True, objective=True)
     torch.cuda.synchronize()
     tol = TOL[dtype]
@@ -101,7 +113,8 @@ def test_linear_smoother_parity(case, dtype):
     ob = r["obj"].cpu().numpy()
     e_ll = np.abs(ll - o["loglik"]).max() / np.abs(o["loglik"]).max()
     e_ob = np.abs(ob - o["mstar"]).max() / np.abs(o["mstar"]).max()
-    msg = f"{case} {dtype}: xs {e_xs:.2e} Ps {e_Ps:.2e} S {e_S:.2e} v {e_v:.2e} ll {e_ll:.2e} obj {e_ob:.2e}"
+    msg = (f"{case} {dtype} chunk {chunk}: xs {e_xs:.2e} Ps {e_Ps:.2e} S {e_S:.2e} v {e_v:.2e} "
+           f"ll {e_ll:.2e} obj {e_ob:.2e}")
     print(msg)
     for e in (e_xs, e_Ps, e_S, e_v):
         assert e <= tol, msg
@@ -188,3 +201,42 @@ def test_gradients_match_oracle_autograd(model):
         em = np.abs(gm_gpu[s] - gm).max() / max(1.0, np.abs(gm).max())
         print(model, s, gl_gpu[s], gl, gm_gpu[s], gm)
         assert el <= 1e-6 and em <= 1e-6, (model, s, gl_gpu[s], gl, gm_gpu[s], gm)
+
+
+def test_schedules_agree_with_gradients():
+    """Fused step with the adjoint at 4, 8 and 16 states per lane: every output
+    agrees across schedules and with the oracle."""
+    ms = _mapscan()
+    wl = workloads.cv_batched(n_seg=11, lmin=5.0, lmax=11.5, seed=21)
+    o = cref.smooth(wl)
+    res = {}
+    for c in (4, 8, 16):
+        p = ms.problem_from_workload(wl, dtype=torch.float64, chunk=c)
+        r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
+        torch.cuda.synchronize()
+        res[c] = {k: v.double().cpu().numpy() for k, v in r.items() if v is not None}
+        assert rel_err(planes_T(r["xs"]), o["xs"]) <= 1e-9
+        assert np.abs(res[c]["loglik"] - o["loglik"]).max() <= 1e-9 * np.abs(o["loglik"]).max()
+    for c in (8, 16):
+        for k in ("xs", "Ps", "loglik", "obj", "g_loglik", "g_obj"):
+            a, b = res[c][k], res[4][k]
+            assert np.abs(a - b).max() <= 1e-10 * max(np.abs(b).max(), 1e-300), (c, k)
+
+
+def test_autotune_records_and_reuses_schedule(tmp_path):
+    ms = _mapscan()
+    wl = workloads.cv_batched(n_seg=9, lmin=6.0, lmax=11.0, seed=77)
+    p = ms.problem_from_workload(wl, dtype=torch.float64)
+    cache = tmp_path / "schedules.txt"
+    c = ms.autotune(p, cache_path=str(cache))
+    assert c in (4, 8, 16)
+    lines = cache.read_text().split("\n")
+    key, chosen, ms_ = lines[0].split()
+    assert int(chosen) == c and float(ms_) > 0
+    assert ms.autotune(p, cache_path=str(cache)) == c        # recorded: not timed again
+    assert len([l for l in cache.read_text().split("\n") if l]) == 1
+    o = cref.smooth(wl)
+    r = ms.smooth(p, covariances=True, loglik=True, objective=True)   # chunk 0: the tuned choice
+    torch.cuda.synchronize()
+    assert rel_err(planes_T(r["xs"]), o["xs"]) <= 1e-9
+    assert rel_err(sym_full(ms, r["Ps"], wl.nx), o["Ps"]) <= 1e-9
