@@ -10,11 +10,16 @@ the seeded inputs of `workloads/`.
              Onsager--Machlup objective, Gauss--Newton iteration; gradients by
              autograd.
   kfs.c      the same filter / smoother / likelihood / objective as plain C,
-             for sizes where a Python loop is too slow (`cref.py` drives it).
+             for sizes where a Python loop is too slow (`cref.py` drives it),
+             and the two-filter smoother of Sec. 4.3 (eq. twofilter): the
+             conditional value function of the later steps by the paper's
+             combination rule, joined with the forward filter.
   models.py  the models' drift/measurement Taylor terms.
 
 Every function is pinned by tests under `tests/test_oracle_*.py` against
 things that do not come from itself: dense Gaussian conditioning, dense least
 squares, the discrete and continuous algebraic Riccati equations, central
-finite differences of a dense likelihood, and nonlinear least squares.
+finite differences of a dense likelihood, and nonlinear least squares; the
+two-filter smoother also against the dense likelihood of the later
+measurements given one state (its backward filter).
 """

@@ -134,3 +134,50 @@ def iterate(wl, n_iter=None, xbar0=None, keep_iterates=False):
     if keep_iterates:
         out["iterates"] = np.stack(its)
     return out
+
+
+def two_filter(wl, xbar=None, suffix=False):
+    """Two-filter smoother (Sec. 4.3, eq. twofilter) of every segment, from the
+    forward filter of `smooth` and the conditional value function of the steps
+    after each state (see `oracle_two_filter` in kfs.c).  Returns dict(xs,
+    Ps, m, P) and, with suffix=True, the run after each state as
+    suf = dict(A, b, C, eta, J) with leading dimension n_states."""
+    lib = _load()
+    nx, ny, nw = wl.nx, wl.ny, wl.nw
+    S = wl.n_seg
+    NS = wl.n_states
+    if xbar is None:
+        xbar = np.zeros((nx, NS))
+    fw = smooth(wl, xbar)
+    t = _terms(wl, xbar)
+    keep = []
+
+    def arg(key):
+        a, st, sg = t[key]
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return [_p(a), ctypes.c_long(st), ctypes.c_long(sg)]
+
+    seg_off = np.ascontiguousarray(wl.seg_off, dtype=np.int64)
+    dt = np.ascontiguousarray(wl.dt, dtype=np.float64)
+    y = np.ascontiguousarray(wl.y.T, dtype=np.float64)
+    m = np.ascontiguousarray(fw["m"]); P = np.ascontiguousarray(fw["P"])
+    xs = np.empty((NS, nx)); Ps = np.empty((NS, nx, nx))
+    suf = np.empty((NS, 3 * nx * nx + 2 * nx)) if suffix else None
+    args = [ctypes.c_int(nx), ctypes.c_int(ny), ctypes.c_int(nw), ctypes.c_long(S), _p(seg_off)]
+    for key in ("F", "c", "L", "W", "H", "r", "R"):
+        args += arg(key)
+    args += [_p(dt), _p(y), _p(m), _p(P), _p(xs), _p(Ps),
+             _p(suf) if suffix else ctypes.c_void_p(None)]
+    lib.oracle_two_filter.restype = ctypes.c_long
+    rc = lib.oracle_two_filter(*args)
+    if rc != S:
+        raise FloatingPointError("oracle: segment %d has a singular two-filter system" % (-rc - 1))
+    out = dict(xs=xs, Ps=Ps, m=fw["m"], P=fw["P"])
+    if suffix:
+        n2 = nx * nx
+        out["suf"] = dict(A=suf[:, :n2].reshape(NS, nx, nx), b=suf[:, n2:n2 + nx],
+                          C=suf[:, n2 + nx:2 * n2 + nx].reshape(NS, nx, nx),
+                          eta=suf[:, 2 * n2 + nx:2 * n2 + 2 * nx],
+                          J=suf[:, 2 * n2 + 2 * nx:].reshape(NS, nx, nx))
+    return out

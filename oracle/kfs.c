@@ -19,6 +19,10 @@
  * step's right end, R a spectral density as in Sec. 2.1).  Written forward:
  * x_k = Phi_k (x_{k-1} + dt c + w) with Phi_k = (I - dt F_k)^{-1}.
  *
+ * oracle_two_filter (at the end of this file) recomputes the smoothed moments
+ * the second way the paper gives (Sec. 4.3, eq. twofilter) from the filter
+ * moments and the conditional value functions of the later steps.
+ *
  * Outputs per segment: filter moments m_k, P_k (k = 0..T, k = 0 is the prior),
  * smoothed moments xs_k, Ps_k, the log marginal likelihood by the prediction
  * error decomposition, and the discretised Onsager--Machlup objective (Sec. 2.1,
@@ -329,5 +333,224 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
   }
   free(mp);
   free(Pp);
+  return n_seg;
+}
+
+/* ---------- two-filter smoother (Sec. 4.3, eq. twofilter) ----------
+ *
+ * For state j of a segment, the steps after it (j+1 .. T) form one
+ * conditional value function of the segment's last state z = x_T and of x_j
+ * (Sec. 4.1, eq. conditionalvalue_linear, later state carrying J and eta):
+ *
+ *   V_j(z, x) = 1/2 z^T J z - z^T eta + 1/2 |x - A z - b|^2_{C^{-1}},
+ *
+ * the combination (Sec. 4.1 rule, earlier run E, later run L) of the one-step
+ * elements of Sec. 4.2 (A = I - dt F, b = -dt c, C = dt Q, eta = dt H^T R^{-1}
+ * (y - r), J = dt H^T R^{-1} H), accumulated here from the segment's end with
+ * the empty run (I, 0, 0, 0, 0).  Eq. twofilter minimises V_j over z first
+ * (combination with the constant element e, kappa -> infinity), which leaves
+ * the backward filter N(x; bbar, Cbar), Cbar = A J^{-1} A^T + C,
+ * bbar = A J^{-1} eta + b, and then combines it with the forward value
+ * function 1/2 x^T S x - x^T v.  Near a segment's end J is singular (one step
+ * observes ny < nx directions), so here both minimisations are done at once:
+ * with lambda = v - S x the stationarity conditions of
+ * 1/2 x^T S x - x^T v + V_j(z, x) over (x, z) read
+ *
+ *   [ I + C S   -A ] [x]   [ b + C v     ]
+ *   [ A^T S      J ] [z] = [ eta + A^T v ]
+ *
+ * (no C^{-1}, no J^{-1}); the same matrix with right-hand side [C; A^T] is
+ * d(x, z)/dv, whose x-block is the smoothed covariance.  Where J is
+ * invertible the x-part equals (I + Cbar S)^{-1} (bbar + Cbar v).
+ *
+ * Inputs as oracle_smooth plus the filter moments m, P it wrote; S = P^{-1},
+ * v = S m (Sec. 2.5).  suf_out (optional, NULL to skip) receives per state the
+ * run after it as A [nx*nx], b [nx], C [nx*nx], eta [nx], J [nx*nx].
+ */
+typedef struct {
+  double A[MX * MX], b[MX], C[MX * MX], eta[MX], J[MX * MX];
+} run_t;
+
+/* out = E . L with E the earlier run (Sec. 4.1 combination rule):
+ *   M = (I + C_L J_E)^{-1}
+ *   A = A_E M A_L,  b = A_E M (b_L + C_L eta_E) + b_E,  C = A_E M C_L A_E^T + C_E,
+ *   eta = A_L^T M^T (eta_E - J_E b_L) + eta_L,  J = A_L^T M^T J_E A_L + J_L. */
+static int run_combine(int n, const run_t *E, const run_t *L, run_t *out) {
+  double X[MX * MX], M[MX * MX], MT[MX * MX], t1[MX * MX], t2[MX * MX], u[MX], w[MX], t3[MX];
+  mm(n, n, n, L->C, E->J, X);
+  for (int i = 0; i < n; ++i) X[i * n + i] += 1.0;
+  if (!inv(n, X, M)) return 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) MT[i * n + j] = M[j * n + i];
+  /* A */
+  mm(n, n, n, M, L->A, t1);
+  mm(n, n, n, E->A, t1, out->A);
+  /* b */
+  mv(n, n, L->C, E->eta, u);
+  for (int i = 0; i < n; ++i) u[i] += L->b[i];
+  mv(n, n, M, u, w);
+  mv(n, n, E->A, w, t3);
+  for (int i = 0; i < n; ++i) out->b[i] = t3[i] + E->b[i];
+  /* C */
+  mm(n, n, n, M, L->C, t1);
+  mm(n, n, n, E->A, t1, t2);
+  mmt(n, n, n, t2, E->A, t1);
+  for (int i = 0; i < n * n; ++i) out->C[i] = t1[i] + E->C[i];
+  symmetrize(n, out->C);
+  /* eta */
+  mv(n, n, E->J, L->b, u);
+  for (int i = 0; i < n; ++i) u[i] = E->eta[i] - u[i];
+  mv(n, n, MT, u, w);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int l = 0; l < n; ++l) s += L->A[l * n + i] * w[l];
+    out->eta[i] = s + L->eta[i];
+  }
+  /* J */
+  mm(n, n, n, E->J, L->A, t1);
+  mm(n, n, n, MT, t1, t2);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < n; ++l) s += L->A[l * n + i] * t2[l * n + j];
+      out->J[i * n + j] = s + L->J[i * n + j];
+    }
+  symmetrize(n, out->J);
+  return 1;
+}
+
+/* Solve a x = b in place (a [n][n] destroyed, b [n][nrhs] overwritten) by
+ * Gaussian elimination with partial pivoting; returns 0 if singular. */
+static int lu_solve(int n, double *a, int nrhs, double *b) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(a[i * n + k]) > fabs(a[p * n + k])) p = i;
+    if (a[p * n + k] == 0.0) return 0;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = a[k * n + j]; a[k * n + j] = a[p * n + j]; a[p * n + j] = t;
+      }
+      for (int j = 0; j < nrhs; ++j) {
+        double t = b[k * nrhs + j]; b[k * nrhs + j] = b[p * nrhs + j]; b[p * nrhs + j] = t;
+      }
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = a[i * n + k] / a[k * n + k];
+      if (f == 0.0) continue;
+      for (int j = k; j < n; ++j) a[i * n + j] -= f * a[k * n + j];
+      for (int j = 0; j < nrhs; ++j) b[i * nrhs + j] -= f * b[k * nrhs + j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i)
+    for (int j = 0; j < nrhs; ++j) {
+      double s = b[i * nrhs + j];
+      for (int l = i + 1; l < n; ++l) s -= a[i * n + l] * b[l * nrhs + j];
+      b[i * nrhs + j] = s / a[i * n + i];
+    }
+  return 1;
+}
+
+long oracle_two_filter(int nx, int ny, int nw, long n_seg, const long *seg_off,
+                       const double *F, long F_step, long F_seg,
+                       const double *c, long c_step, long c_seg,
+                       const double *L, long L_step, long L_seg,
+                       const double *W, long W_step, long W_seg,
+                       const double *H, long H_step, long H_seg,
+                       const double *r, long r_step, long r_seg,
+                       const double *R, long R_step, long R_seg,
+                       const double *dt, const double *y,
+                       const double *m_in, const double *P_in,
+                       double *xs_out, double *Ps_out, double *suf_out) {
+  arr aF = {F, F_step, F_seg}, ac = {c, c_step, c_seg}, aL = {L, L_step, L_seg},
+      aW = {W, W_step, W_seg}, aH = {H, H_step, H_seg}, ar = {r, r_step, r_seg},
+      aR = {R, R_step, R_seg};
+  const int n = nx, n2 = nx * nx, nn = 2 * nx, nr = 1 + nx;
+  const int sufsz = 3 * n2 + 2 * nx;
+  for (long s = 0; s < n_seg; ++s) {
+    const long k0 = seg_off[s], T = seg_off[s + 1] - seg_off[s];
+    const long x0 = k0 + s;
+    run_t suf, tmp, e;
+    memset(&suf, 0, sizeof(suf));
+    for (int i = 0; i < n; ++i) suf.A[i * n + i] = 1.0;
+    for (long j = T; j >= 0; --j) {
+      if (j < T) {
+        /* element of step j+1 (global step index k0 + j) in front of the run */
+        const long k = k0 + j;
+        const double h = dt[k];
+        const double *Fk = at(aF, k, s), *ck = at(ac, k, s), *Lk = at(aL, k, s),
+                     *Wk = at(aW, k, s), *Hk = at(aH, k, s), *rk = at(ar, k, s),
+                     *Rk = at(aR, k, s);
+        double LW[MX * MX], Q[MX * MX], Ri[MX * MX], RiH[MX * MX], d[MX], Rid[MX];
+        for (int i = 0; i < n2; ++i) e.A[i] = -h * Fk[i];
+        for (int i = 0; i < n; ++i) e.A[i * n + i] += 1.0;
+        for (int i = 0; i < n; ++i) e.b[i] = -h * ck[i];
+        mm(n, nw, nw, Lk, Wk, LW);
+        mmt(n, nw, n, LW, Lk, Q);
+        for (int i = 0; i < n2; ++i) e.C[i] = h * Q[i];
+        if (!inv(ny, Rk, Ri)) return -(s + 1);
+        mm(ny, ny, n, Ri, Hk, RiH);
+        for (int i = 0; i < n; ++i)
+          for (int l = 0; l < n; ++l) {
+            double acc = 0.0;
+            for (int q = 0; q < ny; ++q) acc += Hk[q * n + i] * RiH[q * n + l];
+            e.J[i * n + l] = h * acc;
+          }
+        for (int q = 0; q < ny; ++q) d[q] = y[k * ny + q] - rk[q];
+        mv(ny, ny, Ri, d, Rid);
+        for (int i = 0; i < n; ++i) {
+          double acc = 0.0;
+          for (int q = 0; q < ny; ++q) acc += Hk[q * n + i] * Rid[q];
+          e.eta[i] = h * acc;
+        }
+        if (!run_combine(n, &e, &suf, &tmp)) return -(s + 1);
+        suf = tmp;
+      }
+      /* forward value function of state j: S = P^{-1}, v = S m */
+      const double *mj = m_in + (x0 + j) * n, *Pj = P_in + (x0 + j) * n2;
+      double S[MX * MX], v[MX];
+      if (!inv(n, Pj, S)) return -(s + 1);
+      symmetrize(n, S);
+      mv(n, n, S, mj, v);
+      /* joint stationarity system */
+      double Mt[4 * MX * MX], B[2 * MX * (MX + 1)], CS[MX * MX], t[MX];
+      mm(n, n, n, suf.C, S, CS);
+      for (int i = 0; i < n; ++i)
+        for (int l = 0; l < n; ++l) {
+          double ats = 0.0;
+          for (int q = 0; q < n; ++q) ats += suf.A[q * n + i] * S[q * n + l];
+          Mt[i * nn + l] = CS[i * n + l] + (i == l ? 1.0 : 0.0);
+          Mt[i * nn + n + l] = -suf.A[i * n + l];
+          Mt[(n + i) * nn + l] = ats;
+          Mt[(n + i) * nn + n + l] = suf.J[i * n + l];
+        }
+      mv(n, n, suf.C, v, t);
+      for (int i = 0; i < n; ++i) {
+        double atv = 0.0;
+        for (int q = 0; q < n; ++q) atv += suf.A[q * n + i] * v[q];
+        B[i * nr] = suf.b[i] + t[i];
+        B[(n + i) * nr] = suf.eta[i] + atv;
+        for (int l = 0; l < n; ++l) {
+          B[i * nr + 1 + l] = suf.C[i * n + l];
+          B[(n + i) * nr + 1 + l] = suf.A[l * n + i];
+        }
+      }
+      if (!lu_solve(nn, Mt, nr, B)) return -(s + 1);
+      double *xo = xs_out + (x0 + j) * n, *Po = Ps_out + (x0 + j) * n2;
+      for (int i = 0; i < n; ++i) {
+        xo[i] = B[i * nr];
+        for (int l = 0; l < n; ++l) Po[i * n + l] = B[i * nr + 1 + l];
+      }
+      symmetrize(n, Po);
+      if (suf_out) {
+        double *o = suf_out + (x0 + j) * sufsz;
+        memcpy(o, suf.A, sizeof(double) * n2);
+        memcpy(o + n2, suf.b, sizeof(double) * n);
+        memcpy(o + n2 + n, suf.C, sizeof(double) * n2);
+        memcpy(o + 2 * n2 + n, suf.eta, sizeof(double) * n);
+        memcpy(o + 2 * n2 + 2 * n, suf.J, sizeof(double) * n2);
+      }
+    }
+  }
   return n_seg;
 }

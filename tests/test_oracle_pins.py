@@ -239,3 +239,113 @@ def test_lorenz_iterates_c_and_torch_agree_and_decrease():
         obj = [ref.map_objective_nonlinear("lorenz63", seg["theta"], x, seg["dt"], seg["y"],
                                            seg["m0"], seg["P0"], 3).item() for x in its]
         assert obj[-1] <= obj[1]
+
+
+# ------------------------------------------------------------------ two-filter smoother
+def _tf_cases():
+    return _cases() + [
+        workloads.cv_batched(lens=[9, 1, 14], d=2, dt=0.05, seed=25),       # segments, T = 1
+        workloads.linear_random(T=12, nx=2, ny=2, nw=1, seed=26, n_seg=2),  # H square
+    ]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_two_filter_equals_dense_conditioning(case):
+    """Sec. 4.3 eq. twofilter: forward value function combined with the
+    conditional value function of the later steps gives the posterior of the
+    discrete model, state by state (dense conditioning of the joint Gaussian)."""
+    wl = _tf_cases()[case]
+    o = cref.two_filter(wl)
+    nx = wl.nx
+    for s in range(wl.n_seg):
+        mean, cov, _ = _dense.dense_posterior(wl, s)
+        st = wl.seg_states(s)
+        T = st.stop - st.start - 1
+        dcov = np.stack([cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] for k in range(T + 1)])
+        assert np.abs(o["xs"][st] - mean).max() <= 1e-11 * max(1.0, np.abs(mean).max())
+        assert np.abs(o["Ps"][st] - dcov).max() <= 1e-11 * max(1.0, np.abs(dcov).max())
+
+
+def _later_likelihood(wl, s, k):
+    """p(y_{k+1..T} | x_k) as a Gaussian in x_k (precision, precision * mean),
+    by dense conditioning of the joint Gaussian; the prior drops out because
+    the later measurements depend on the past only through x_k."""
+    mu, Sx, Hb, Rb, rb = _dense.joint_gaussian(wl, s)
+    nx, ny = wl.nx, wl.ny
+    st = wl.seg_steps(s)
+    yv = wl.y[:, st].T.reshape(-1)
+    rows = slice(k * ny, None)
+    Hl, Rl, rl, yl = Hb[rows], Rb[rows, rows], rb[rows], yv[rows]
+    ks = slice(k * nx, (k + 1) * nx)
+    Cxx = Sx[ks, ks]
+    Cyx = Hl @ Sx[:, ks]
+    Cyy = Hl @ Sx @ Hl.T + Rl
+    G = np.linalg.solve(Cxx, Cyx.T).T
+    delta = Hl @ mu + rl - G @ mu[ks]
+    Sig = Cyy - G @ Cyx.T
+    prec = G.T @ np.linalg.solve(Sig, G)
+    info = G.T @ np.linalg.solve(Sig, yl - delta)
+    return prec, info
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 5])
+def test_backward_filter_equals_later_measurement_likelihood(case):
+    """The kappa -> infinity combination of Sec. 4.3: Cbar = A J^{-1} A^T + C,
+    bbar = A J^{-1} eta + b (with the + b of the first element; the printed
+    bbar_0 has no b_0) is the likelihood of the later measurements as a
+    function of x_k, N(x_k; bbar, Cbar) up to a constant."""
+    wl = _tf_cases()[case]
+    o = cref.two_filter(wl, suffix=True)
+    suf = o["suf"]
+    T = wl.seg_off[1] - wl.seg_off[0]
+    checked = 0
+    for k in (0, T // 2, T - 3):
+        A, b, C, eta, J = (suf[n][k] for n in ("A", "b", "C", "eta", "J"))
+        assert np.linalg.cond(J) < 1e10
+        Ji = np.linalg.inv(J)
+        Cbar = A @ Ji @ A.T + C
+        bbar = A @ Ji @ eta + b
+        prec, info = _later_likelihood(wl, 0, k)
+        Cd = np.linalg.inv(prec)
+        bd = Cd @ info
+        assert np.abs(Cbar - Cd).max() <= 1e-9 * np.abs(Cd).max()
+        assert np.abs(bbar - bd).max() <= 1e-9 * max(1.0, np.abs(bd).max())
+        checked += 1
+    assert checked == 3
+
+
+@pytest.mark.parametrize("case", [0, 2, 5])
+def test_two_filter_joint_solve_equals_printed_formula(case):
+    """Where the later run's J is invertible the oracle's joint minimisation
+    equals eq. twofilter as printed: x = (I + Cbar S)^{-1} (bbar + Cbar v)
+    with S = P^{-1}, v = P^{-1} m of the forward filter (Sec. 2.5)."""
+    wl = _tf_cases()[case]
+    o = cref.two_filter(wl, suffix=True)
+    suf = o["suf"]
+    nx = wl.nx
+    n = 0
+    for k in range(wl.n_states):
+        J = suf["J"][k]
+        if np.linalg.cond(J) > 1e8:
+            continue
+        Ji = np.linalg.inv(J)
+        Cbar = suf["A"][k] @ Ji @ suf["A"][k].T + suf["C"][k]
+        bbar = suf["A"][k] @ Ji @ suf["eta"][k] + suf["b"][k]
+        S = np.linalg.inv(o["P"][k])
+        v = S @ o["m"][k]
+        x = np.linalg.solve(np.eye(nx) + Cbar @ S, bbar + Cbar @ v)
+        assert np.abs(x - o["xs"][k]).max() <= 1e-9 * max(1.0, np.abs(x).max())
+        n += 1
+    assert n >= wl.n_states // 2
+
+
+def test_two_filter_end_state_is_filter():
+    """At a segment's last state the later run is empty (I, 0, 0, 0, 0) and the
+    two-filter estimate is the filter's."""
+    wl = _tf_cases()[3]
+    o = cref.two_filter(wl, suffix=True)
+    last = wl.n_states - 1
+    assert np.array_equal(o["suf"]["A"][last], np.eye(wl.nx))
+    assert not o["suf"]["J"][last].any() and not o["suf"]["C"][last].any()
+    assert np.abs(o["xs"][last] - o["m"][last]).max() <= 1e-12 * np.abs(o["m"][last]).max()
+    assert np.abs(o["Ps"][last] - o["P"][last]).max() <= 1e-12 * np.abs(o["P"][last]).max()
