@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 3
+#define MAPSCAN_ABI_VERSION 4
 #define MAPSCAN_TILE 1024
 
 typedef enum {
@@ -185,6 +185,25 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
                       double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* Two-filter smoother (Sec. 4.3, eq. twofilter): the same MAP trajectory as
+ * map_smooth, recovered the paper's second way.  The filter scan gives the
+ * forward value function (S_k, v_k); a reverse segmented scan with the same
+ * combination rule (Sec. 4.1) gives, for every state, the conditional value
+ * function of the steps after it up to its segment's end (the backward
+ * filter); each state then combines the two.  Eq. twofilter first minimises
+ * the later run over the segment's last state, which needs the run's J to be
+ * invertible; a single step observes only ny directions, so the library
+ * minimises over both ends jointly instead, which equals the printed formula
+ * wherever that J is invertible and stays defined where it is not.
+ *   S, v   out, as map_filter_scan
+ *   xs     out tiled [nx] per state: MAP trajectory = smoothed means
+ *   Ps     optional out tiled [nx(nx+1)/2] per state: smoothed covariances
+ *   loglik optional out [n_seg] (double), as map_filter_scan.
+ * Costs more than map_smooth (one more element combination per state); no
+ * objective or gradients here (map_smooth gives them). */
+map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                                 double* loglik, void* ws, size_t ws_bytes, void* stream);
+
 /* Iterated Taylor linearisation (Sec. 4.4): xbar^(0) = xbar0 (NULL: m0 of each
  * segment at every state), then n_iter times: linearise about xbar, solve
  * with map_smooth, xbar <- xs.  xbar_buf (tiled [nx] per state) is caller scratch that
@@ -226,7 +245,8 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
  * kind, the number of timed launches and their summed duration in ms.
  * Kinds: 0 filter up-sweep, 1 filter fix-up, 2 fused filter fix-up +
  * trajectory up-sweep, 3 trajectory up-sweep from stored S, v, 4 trajectory
- * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing). */
+ * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing), 7 filter
+ * fix-up + backward-filter up-sweep (two-filter), 8 two-filter combination. */
 map_status map_profile_enable(int32_t capacity);
 map_status map_profile_reset(void);
 map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms);

@@ -26,6 +26,7 @@ from . import _lib
 from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
+           "two_filter_smooth",
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
            "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
@@ -314,6 +315,25 @@ def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False
                               _stream()))
     return _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm),
                 natural)
+
+
+def two_filter_smooth(p: Problem, covariances=True, loglik=True, out=None, natural=True):
+    """Two-filter smoother (Sec. 4.3, eq. twofilter): filter scan, backward
+    filter (reverse segmented scan of the later steps) and their per-state
+    combination.  Same trajectory as `smooth`; `out` as there."""
+    lib = _lib.load()
+    ws = p.workspace()
+    o = out or {}
+    S = o.get("S") if o.get("S") is not None else p._tiled(p.nsym)
+    v = o.get("v") if o.get("v") is not None else p._tiled(p.nx)
+    xs = o.get("xs") if o.get("xs") is not None else p._tiled(p.nx)
+    Ps = (o.get("Ps") if o.get("Ps") is not None else p._tiled(p.nsym)) \
+        if covariances else None
+    ll = (o.get("loglik") if o.get("loglik") is not None
+          else p._empty(p.n_seg, dtype=torch.float64)) if loglik else None
+    _lib.check(lib.map_two_filter_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs),
+                                         _ptr(Ps), _ptr(ll), _ptr(ws), ws.numel(), _stream()))
+    return _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll), natural)
 
 
 def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, loglik=True,

@@ -431,4 +431,200 @@ MS_DEV void traj_step(const T (&G)[N][N], const T (&beta)[N], const T (&Lam)[N][
   }
 }
 
+// ------------------------------------------------------------------ two-filter smoother
+// The steps after a state form one run s whose later state is the segment's
+// last state z; the two-filter smoother (Sec. 4.3, eq. twofilter) combines it
+// with the forward value function of the state.
+
+// s <- f . s: the element of one step in front of a later run s (the Sec. 4.1
+// rule with E = f).  Writing the step's measurement terms as J_f = H^T D H,
+// eta_f = H^T D e (D = dt R^{-1}, e = y - r), the factor M = (I + C_s J_f)^{-1}
+// only needs the NY x NY matrix Y = R / dt + H C_s H^T (push-through identity):
+//   M = I - K Y^{-1} H,  K = C_s H^T;   M^T J_f = H^T Y^{-1} H;   M^T H^T D = H^T Y^{-1}
+// hence, with A_f = I - dt F, b_f = -dt c, C_f = V V^T,
+//   A   = A_f (A_s - K Y^{-1} H A_s)
+//   b   = A_f (u - K Y^{-1} H u) + b_f,      u = b_s + K D e
+//   C   = A_f (C_s - K Y^{-1} K^T) A_f^T + V V^T
+//   eta = (H A_s)^T Y^{-1} (e - H b_s) + eta_s
+//   J   = (H A_s)^T Y^{-1} (H A_s) + J_s.
+template <typename T, int N, int NY, int NW>
+MS_DEV void prepend_step(const Step<T, N, NY, NW>& st, const T (&y)[NY], Elem<T, N>& s) {
+  const T dt = st.dt;
+  T K[N][NY];
+  mmt(s.C, st.H, K);  // C_s H^T
+  T Y[NY][NY];
+  mm(st.H, K, Y);
+  const T rdt = rcp(dt);
+#pragma unroll
+  for (int a = 0; a < NY; ++a)
+#pragma unroll
+    for (int b = 0; b < NY; ++b) Y[a][b] = fma_(st.R[a][b], rdt, Y[a][b]);
+  T Ly[NY][NY], dy[NY];
+  chol(Y, Ly, dy);
+  // Yh = Ly^{-1} H A_s; J and the A update share it
+  T Yh[NY][N];
+  mm(st.H, s.A, Yh);
+  trsm_lower(Ly, dy, Yh);
+  T Jn[N][N];
+  mtm_sym(Yh, Yh, Jn);
+  // eta: Yh^T Ly^{-1} (e - H b_s)
+  T e[NY], w[NY], Hb[NY];
+  mv(st.H, s.b, Hb);
+#pragma unroll
+  for (int a = 0; a < NY; ++a) {
+    e[a] = y[a] - st.r[a];
+    w[a] = e[a] - Hb[a];
+  }
+  trsv_lower(Ly, dy, w);
+  T en[N];
+  mtv(Yh, w, en);
+  // b: u = b_s + K D e,  M u = u - K Y^{-1} H u
+  T De[NY], u[N];
+  mv(st.Rinv, e, De);
+#pragma unroll
+  for (int a = 0; a < NY; ++a) De[a] *= dt;
+  mv(K, De, u);
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] += s.b[i];
+  T zu[NY], Ku[N];
+  mv(st.H, u, zu);
+  trsv_lower(Ly, dy, zu);
+  trsv_upper_t(Ly, dy, zu);
+  mv(K, zu, Ku);
+  T Mu[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) Mu[i] = u[i] - Ku[i];
+  // A: A_s - K Ly^{-T} Yh
+  trsm_upper_t(Ly, dy, Yh);  // Yh <- Y^{-1} H A_s
+  T KX[N][N], MA[N][N];
+  mm(K, Yh, KX);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) MA[i][j] = s.A[i][j] - KX[i][j];
+  // C: C_s - (Ly^{-1} K^T)^T (Ly^{-1} K^T)
+  T Yk[NY][N];
+#pragma unroll
+  for (int a = 0; a < NY; ++a)
+#pragma unroll
+    for (int i = 0; i < N; ++i) Yk[a][i] = K[i][a];
+  trsm_lower(Ly, dy, Yk);
+  T KYK[N][N], MC[N][N];
+  mtm_sym(Yk, Yk, KYK);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) MC[i][j] = s.C[i][j] - KYK[i][j];
+  // outer factor A_f = I - dt F:  A_f X = X - dt F X
+  T FX[N][N], FMC[N][N], Fm[N];
+  mm(st.F, MA, FX);
+  mm(st.F, MC, FMC);
+  mv(st.F, Mu, Fm);
+  T AMC[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    s.b[i] = fma_(-dt, Fm[i] + st.c[i], Mu[i]);
+    s.eta[i] = en[i] + s.eta[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      s.A[i][j] = fma_(-dt, FX[i][j], MA[i][j]);
+      AMC[i][j] = fma_(-dt, FMC[i][j], MC[i][j]);
+      s.J[i][j] = Jn[i][j] + s.J[i][j];
+    }
+  }
+  // C = AMC A_f^T + V V^T = AMC - dt AMC F^T + V V^T
+  T AMCF[N][N], VV[N][N];
+  mmt(AMC, st.F, AMCF);
+  mmt_sym(st.V, st.V, VV);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const T c = fma_(-dt, AMCF[i][j], AMC[i][j]) + VV[i][j];
+      s.C[i][j] = c;
+      s.C[j][i] = c;
+    }
+}
+
+// Two-filter estimate of one state from its forward value function (S, v)
+// and the run s of the steps after it.  Eq. twofilter minimises s over the
+// far end z first, x = (I + Cbar S)^{-1} (bbar + Cbar v) with
+// Cbar = A J^{-1} A^T + C and bbar = A J^{-1} eta + b; J is singular near a
+// segment's end, so the joint minimum over (x, z) of
+// 1/2 x^T S x - x^T v + V_s(z, x) is taken instead, eliminating x first:
+//   x = beta + G z,  G = (I + C S)^{-1} A,  beta = (I + C S)^{-1} (b + C v)
+//   Shat z = vhat,   Shat = J + A^T S (I + C S)^{-1} A,  vhat = eta + A^T (v - S beta)
+// ((Shat, vhat) is (S, v) carried through s: the filter at the segment's
+// last state).  The same elimination applied to d(x, z)/dv gives the
+// smoothed covariance P = Lam + G Shat^{-1} G^T, Lam = (I + C S)^{-1} C.
+// Where J is invertible this equals eq. twofilter exactly.
+template <typename T, int N, bool kCov>
+MS_DEV void two_filter_point(const T (&S)[N][N], const T (&v)[N], const Elem<T, N>& s, T (&x)[N],
+                             T (&P)[N][N]) {
+  T X[N][N], Mi[N][N];
+  mm(s.C, S, X);
+#pragma unroll
+  for (int i = 0; i < N; ++i) X[i][i] += T(1);
+  inv(X, Mi);  // det(I + C S) >= 1
+  T G[N][N];
+  mm(Mi, s.A, G);
+  T u[N], beta[N];
+  mv(s.C, v, u);
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] += s.b[i];
+  mv(Mi, u, beta);
+  T SG[N][N], Sh[N][N];
+  mm(S, G, SG);
+  mtm_sym(s.A, SG, Sh);
+  T Sb[N], w[N], vh[N];
+  mv(S, beta, Sb);
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = v[i] - Sb[i];
+  mtv(s.A, w, vh);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    vh[i] += s.eta[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) Sh[i][j] += s.J[i][j];
+  }
+  T Ls[N][N], ds[N];
+  chol(Sh, Ls, ds);
+  trsv_lower(Ls, ds, vh);
+  trsv_upper_t(Ls, ds, vh);  // vh <- z
+  T Gz[N];
+  mv(G, vh, Gz);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = beta[i] + Gz[i];
+  if constexpr (kCov) {
+    T Lam[N][N];
+    mmt_sym(Mi, s.C, Lam);  // (I + C S)^{-1} C, symmetric
+    T Yg[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Yg[i][j] = G[j][i];
+    trsm_lower(Ls, ds, Yg);
+    T GG[N][N];
+    mtm_sym(Yg, Yg, GG);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) P[i][j] = Lam[i][j] + GG[i][j];
+  }
+}
+
+// Segmented product for a reverse scan whose runs must stop at segment
+// starts: (P, f) is the run from a position up to the first segment start
+// at or after it (exclusive) and f whether one occurred.  (P, f) of a range X
+// followed by a range Y: f = f_X | f_Y, P = f_X ? P_X : P_X . P_Y.
+template <typename T, int N>
+MS_DEV void seg_append(Elem<T, N>& P, T& f, const Elem<T, N>& Py, T fy) {
+  if (f == T(0)) {
+    Elem<T, N> t;
+    combine(P, Py, t);
+    P = t;
+  }
+  f = f > fy ? f : fy;
+}
+
 }  // namespace ms

@@ -194,9 +194,11 @@ struct LaneTiled {
   int64_t C;  // components per lane
   MS_DEV int64_t at(int64_t g, int64_t c) const { return ((g >> 6) * C + c) * kWave + (g & (kWave - 1)); }
 };
-template <typename T, int N>
-MS_DEVONLY void lt_store_elem(T* base, int64_t g, const Elem<T, N>& e) {
-  const LaneTiled L{ElemSz<N>::n};
+// kFlag: one more component after the element (the segment flag of the
+// reverse scan of the two-filter smoother).
+template <typename T, int N, bool kFlag = false>
+MS_DEVONLY void lt_store_elem(T* base, int64_t g, const Elem<T, N>& e, T flag = T(0)) {
+  const LaneTiled L{ElemSz<N>::n + (kFlag ? 1 : 0)};
   int c = 0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
@@ -214,10 +216,11 @@ MS_DEVONLY void lt_store_elem(T* base, int64_t g, const Elem<T, N>& e) {
   for (int r = 0; r < N; ++r)
 #pragma unroll
     for (int q = 0; q <= r; ++q) wt_store(&base[L.at(g, c++)], e.J[r][q]);
+  if constexpr (kFlag) wt_store(&base[L.at(g, c)], flag);
 }
-template <typename T, int N>
-MS_DEVONLY void lt_load_elem(const T* base, int64_t g, Elem<T, N>& e) {
-  const LaneTiled L{ElemSz<N>::n};
+template <typename T, int N, bool kFlag = false>
+MS_DEVONLY void lt_load_elem(const T* base, int64_t g, Elem<T, N>& e, T* flag = nullptr) {
+  const LaneTiled L{ElemSz<N>::n + (kFlag ? 1 : 0)};
   int c = 0;
 #pragma unroll
   for (int r = 0; r < N; ++r)
@@ -235,6 +238,7 @@ MS_DEVONLY void lt_load_elem(const T* base, int64_t g, Elem<T, N>& e) {
   for (int r = 0; r < N; ++r)
 #pragma unroll
     for (int q = 0; q <= r; ++q) { e.J[r][q] = base[L.at(g, c++)]; e.J[q][r] = e.J[r][q]; }
+  if constexpr (kFlag) *flag = base[L.at(g, c)];
 }
 template <typename T, int N>
 MS_DEVONLY void lt_store_aff(T* base, int64_t g, const Aff<T, N>& a) {
@@ -750,6 +754,116 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
   }
 }
 
+// Backward-filter tile scan of the two-filter smoother, run by the last
+// block: for every tile, the run after it up to the next segment start
+// (segmented reverse scan, see seg_append).  Tile aggregates carry their flag
+// as component ElemSz of the plane set.
+template <typename T, int N>
+MS_DEVONLY void load_selem(const T* base, int64_t ld, int64_t i, Elem<T, N>& e, T& f) {
+  load_elem(base, ld, i, e);
+  f = base[ElemSz<N>::n * ld + i];
+}
+
+template <typename T, int N>
+MS_DEVONLY void suffix_tile_scan(const Ws<T>& ws) {
+  constexpr int E = ElemSz<N>::n;
+  __shared__ T s_w[4][E + 1];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  const int64_t nt = ws.n_tiles;
+  const int64_t K = (nt + kBlock - 1) / kBlock;
+  const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
+  Elem<T, N> acc, o, nx_;
+  T af = T(0), of = T(0), nf = T(0);
+  if (t0 < t1) {
+    load_selem(ws.stile_agg, nt, t0, acc, af);
+    if (t0 + 1 < t1) load_selem(ws.stile_agg, nt, t0 + 1, nx_, nf);
+    for (int64_t t = t0 + 1; t < t1; ++t) {
+      o = nx_;
+      of = nf;
+      if (t + 1 < t1) load_selem(ws.stile_agg, nt, t + 1, nx_, nf);  // one tile ahead
+      seg_append(acc, af, o, of);
+    }
+  } else {
+    elem_identity(acc);
+  }
+  // reverse inclusive scan over the lanes: acc <- acc (+) lanes to the right
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int src = lane + d < kWave ? lane + d : lane;
+    shfl_elem(o, acc, src);
+    of = shfl(af, src);
+    if (lane + d < kWave) seg_append(acc, af, o, of);
+  }
+  if (lane == 0) {
+    T* w = s_w[wv];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) w[c++] = acc.A[r][q];
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[c++] = acc.b[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) w[c++] = acc.C[r][q];
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[c++] = acc.eta[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) w[c++] = acc.J[r][q];
+    w[c] = af;
+  }
+  __syncthreads();
+  // run after this thread's tiles: lanes to the right, then waves to the right
+  Elem<T, N> ex;
+  T exf;
+  shfl_elem(ex, acc, lane + 1 < kWave ? lane + 1 : lane);
+  exf = shfl(af, lane + 1 < kWave ? lane + 1 : lane);
+  if (lane == kWave - 1) {
+    elem_identity(ex);
+    exf = T(0);
+  }
+  for (int w = wv + 1; w < 4; ++w) {
+    const T* sw = s_w[w];
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) o.A[r][q] = sw[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r) o.b[r] = sw[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) { o.C[r][q] = sw[c++]; o.C[q][r] = o.C[r][q]; }
+#pragma unroll
+    for (int r = 0; r < N; ++r) o.eta[r] = sw[c++];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) { o.J[r][q] = sw[c++]; o.J[q][r] = o.J[r][q]; }
+    seg_append(ex, exf, o, sw[c]);
+  }
+  // runs after each of this thread's tiles, right to left (the one before
+  // its first tile is not needed)
+  if (t1 - 1 > t0) load_selem(ws.stile_agg, nt, t1 - 1, nx_, nf);
+  for (int64_t t = t1 - 1; t >= t0; --t) {
+    store_elem(ws.stile_carry, nt, t, ex);
+    if (t > t0) {
+      o = nx_;
+      of = nf;
+      if (t - 1 > t0) load_selem(ws.stile_agg, nt, t - 1, nx_, nf);
+      // ex <- tile t (+) ex
+      T f2 = of;
+      seg_append(o, f2, ex, exf);
+      ex = o;
+      exf = f2;
+    }
+  }
+}
+
 // --------------------------------------------------------------------------- pass A
 // Zero the per-segment accumulators over the whole grid.  The filter
 // up-sweep does this for the passes that follow it (it runs before any of
@@ -832,7 +946,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
 }
 
 // --------------------------------------------------------------------------- pass B
-enum : int { kModeFilter = 0, kModeFused = 1, kModeTrajOnly = 2 };
+// kModeTwoFilter: the filter fix-up plus the up-sweep of the backward filter
+// of the two-filter smoother (the runs of later steps, Sec. 4.3).
+enum : int { kModeFilter = 0, kModeFused = 1, kModeTrajOnly = 2, kModeTwoFilter = 3 };
 
 struct FilterOut {
   void* S;    // [Sym][n_states]
@@ -886,7 +1002,8 @@ template <typename TS, typename T, class M, int kMode>
 __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, FilterOut fo, Acc acc) {
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr bool kFilter = kMode != kModeTrajOnly;
-  constexpr bool kTraj = kMode != kModeFilter;
+  constexpr bool kTraj = kMode == kModeFused || kMode == kModeTrajOnly;
+  constexpr bool kSuf = kMode == kModeTwoFilter;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
@@ -909,6 +1026,11 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   }
   Aff<T, N> sagg;
   aff_identity(sagg);
+  // backward filter: the run from the chunk's first state up to the first
+  // segment start in the chunk (exclusive), and whether there is one
+  Elem<T, N> pagg;
+  T pf = T(0);
+  if constexpr (kSuf) elem_identity(pagg);
   double ll = 0.0;
   int64_t seg_acc = -1;
   if (j0 < j1) {
@@ -949,6 +1071,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           }
           T m0[N], P0i[N][N];
           cur.prior(p, S, v, m0, P0i);
+          if constexpr (kSuf) pf = T(1);
         } else {
           Step<T, N, NY, NW> st;
           const T(&y)[NY] = rc.y;
@@ -962,6 +1085,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           } else {
             info_step<T, N, NW, false>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           }
+          if constexpr (kSuf) {
+            if (pf == T(0)) fold_fresh(pagg, f);
+          }
           if (fo.want_loglik) {
             T vp[N];
 #pragma unroll
@@ -972,8 +1098,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
 #pragma unroll
           for (int r = 0; r < N; ++r) v[r] = vn[r];
         }
-        tstore_sym<TS, T, N, kTraj>(So, Sym<N>::n, i, S);
-        tstore_vec<TS, T, N, kTraj>(vo, N, i, v);
+        tstore_sym<TS, T, N, kTraj || kSuf>(So, Sym<N>::n, i, S);
+        tstore_vec<TS, T, N, kTraj || kSuf>(vo, N, i, v);
         if (kMode == kModeFilter && mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
@@ -1052,6 +1178,35 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
     if (g < ws.n_lanes) lt_store_aff(ws.slane_pre, g, o);
     if (last) {
       traj_tile_scan<T, N>(ws);
+      release_counter(ws.counters + kCountersTraj);
+    }
+  }
+  if constexpr (kSuf) {
+    // reverse in-tile segmented scan of the backward-filter runs
+    Elem<T, N> o;
+    T of;
+#pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int src = lane + d < kWave ? lane + d : lane;
+      shfl_elem(o, pagg, src);
+      of = shfl(pf, src);
+      if (lane + d < kWave) seg_append(pagg, pf, o, of);
+    }
+    shfl_elem(o, pagg, lane + 1 < kWave ? lane + 1 : lane);
+    of = shfl(pf, lane + 1 < kWave ? lane + 1 : lane);
+    if (lane == kWave - 1) {
+      elem_identity(o);
+      of = T(0);
+    }
+    if (lane == 0 && tile < ws.n_tiles) {
+      store_elem<T, N, true>(ws.stile_agg, ws.n_tiles, tile, pagg);
+      wt_store(&ws.stile_agg[ElemSz<N>::n * ws.n_tiles + tile], pf);
+    }
+    const bool last = arrive_last(ws.counters + kCountersTraj);
+    // read only by the next kernel: written after the arrival (see the filter up-sweep)
+    if (g < ws.n_lanes) lt_store_elem<T, N, true>(ws.slane_pre, g, o, of);
+    if (last) {
+      suffix_tile_scan<T, N>(ws);
       release_counter(ws.counters + kCountersTraj);
     }
   }
@@ -1324,6 +1479,89 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     }
   }
   if (to.want_obj || kGrad) flush_wave<KV>(seg_acc, val, dst, dstr);
+}
+
+// --------------------------------------------------------------------------- pass C'
+// Two-filter combination (Sec. 4.3, eq. twofilter).  Each lane gets the run
+// of the steps after its chunk (its in-tile run and the tile's run, both from
+// the backward-filter up-sweep) and walks its chunk backwards: the state's
+// forward value function (S, v) and the run after it give x*_k and P^s_k;
+// then the step that ends at the state is put in front of the run.
+template <typename TS, typename T, class M, bool kCov>
+__global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws, TrajOut to) {
+  constexpr int N = M::NX, NY = M::NY, NW = M::NW;
+  const int64_t g = logical_block() * kBlock + threadIdx.x;
+  const int64_t tile = g >> 6;
+  const int64_t j0 = g * ws.chunk;
+  const int64_t ns = p.n_states;
+  const TS* Si = static_cast<const TS*>(to.S);
+  const TS* vi = static_cast<const TS*>(to.v);
+  TS* xo = static_cast<TS*>(to.xs);
+  TS* Po = static_cast<TS*>(to.Ps);
+  const int64_t j1 = lane_end(g, ws.n_lanes, ns, ws.chunk);
+  if (j0 >= j1) return;
+  // the run after the chunk: in-tile part, then (unless it reached a
+  // segment start) the tile's
+  Elem<T, N> s;
+  {
+    T f;
+    lt_load_elem<T, N, true>(ws.slane_pre, g, s, &f);
+    if (f == T(0)) {
+      Elem<T, N> c, t;
+      load_elem(ws.stile_carry, ws.n_tiles, tile, c);
+      combine(s, c, t);
+      s = t;
+    }
+  }
+  const int64_t il = j1 - 1;
+  Cursor<TS, T, M> cur;
+  cur.init(p, il);
+  // filter moments and step inputs of a state, in three rotating buffers
+  // refilled three states ahead (as in the trajectory fix-up)
+  struct Ahead {
+    T S[N][N];
+    T v[N];
+    typename Cursor<TS, T, M>::Raw r;
+  } q0, q1, q2;
+  auto refill = [&](int64_t k, Ahead& q) {
+    const int64_t ia = k >= j0 ? k : j0;
+    tload_sym(Si, Sym<N>::n, ia, q.S);
+    tload_vec(vi, N, ia, q.v);
+    cur.fetch(p, ia, q.r);
+  };
+  refill(il, q0);
+  refill(il - 1, q1);
+  refill(il - 2, q2);
+  auto body = [&](int64_t i, Ahead& q) {
+    T x[N], P[N][N];
+    two_filter_point<T, N, kCov>(q.S, q.v, s, x, P);
+    tstore_vec(xo, N, i, x);
+    if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
+    if (i > j0) {
+      if (cur.is_head(i)) {
+        // state i - 1 ends the previous segment: nothing comes after it
+        elem_identity(s);
+        cur.prev(p);
+      } else {
+        Step<T, N, NY, NW> st;
+        const typename Cursor<TS, T, M>::Raw rc = q.r;
+        cur.terms(p, i, rc, st);
+        prepend_step(st, rc.y, s);
+      }
+    }
+    refill(i - 3, q);
+  };
+  drain_vmem();
+  int64_t i = il;
+  for (; i - 2 >= j0; i -= 3) {
+    body(i, q0);
+    body(i - 1, q1);
+    body(i - 2, q2);
+  }
+  for (; i >= j0; --i) {
+    body(i, q0);
+    q0 = q1;
+  }
 }
 
 // --------------------------------------------------------------------------- misc

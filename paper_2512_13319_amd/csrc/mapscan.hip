@@ -267,6 +267,13 @@ struct DoSmooth {
     return hip_status(Runner<TS, T, M>::smooth(p, a), "map_smooth");
   }
 };
+struct DoTwoFilter {
+  const map_problem& p;
+  SmoothArgs a;
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::two_filter(p, a), "map_two_filter_smooth");
+  }
+};
 struct DoInitX {
   const map_problem& p;
   void* xb;
@@ -336,6 +343,17 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return dispatch(*p, DoSmooth{*p, a});
+}
+
+map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                                 double* loglik, void* ws, size_t ws_bytes, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
+               static_cast<hipStream_t>(stream), sched::resolve(*p)};
+  return dispatch(*p, DoTwoFilter{*p, a});
 }
 
 map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const void* xbar0,

@@ -42,13 +42,17 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   const int64_t sym = nx * (nx + 1) / 2;
   const int64_t elem = nx * nx + 2 * nx + 2 * sym;
   const int64_t aff = nx * nx + nx + sym;
+  // the reverse-scan regions serve the trajectory maps (RTS form) and the
+  // flagged backward-filter runs (two-filter form)
+  const int64_t rlane = aff > elem + 1 ? aff : elem + 1;
+  const int64_t rcarry = nx + sym > elem ? nx + sym : elem;
   const size_t sizes[7] = {256,
                            size_t(elem * w.n_lanes) * sz,
                            size_t(elem * w.n_tiles) * sz,
                            size_t((sym + nx) * w.n_tiles) * sz,
-                           size_t(aff * w.n_lanes) * sz,
-                           size_t(aff * w.n_tiles) * sz,
-                           size_t((nx + sym) * w.n_tiles) * sz};
+                           size_t(rlane * w.n_lanes) * sz,
+                           size_t(rlane * w.n_tiles) * sz,
+                           size_t(rcarry * w.n_tiles) * sz};
   size_t o = 0;
   for (int i = 0; i < 7; ++i) {
     w.off[i] = o;
@@ -83,7 +87,9 @@ enum ProfKind : int {
   kProfTrajDown = 4,
   kProfTrajDownGrad = 5,
   kProfAux = 6,
-  kProfKinds = 7
+  kProfTwoFilterUp = 7,
+  kProfTwoFilterDown = 8,
+  kProfKinds = 9
 };
 void prof_begin(int kind, hipStream_t st);
 void prof_end(int kind, hipStream_t st);
@@ -95,6 +101,7 @@ struct Runner {
   static hipError_t filter(const map_problem& p, const SmoothArgs& a);
   static hipError_t smoother(const map_problem& p, const SmoothArgs& a, bool grad);
   static hipError_t smooth(const map_problem& p, const SmoothArgs& a);
+  static hipError_t two_filter(const map_problem& p, const SmoothArgs& a);
   static hipError_t init_xbar(const map_problem& p, void* xbar, hipStream_t st);
 };
 

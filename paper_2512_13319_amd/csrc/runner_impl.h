@@ -186,6 +186,33 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 
+// Two-filter smoother: filter up-sweep, filter fix-up with the backward
+// filter's up-sweep, two-filter combination.
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& a) {
+  Prob<TS> p = make_prob<TS>(q);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
+  const unsigned g = grid_for(w.n_tiles);
+  prof_begin(kProfFilterUp, a.stream);
+  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
+  prof_end(kProfFilterUp, a.stream);
+  MS_CHECK(hipGetLastError());
+  FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
+  Acc acc{a.loglik, nullptr, nullptr, nullptr};
+  prof_begin(kProfTwoFilterUp, a.stream);
+  k_filter_down<TS, T, M, kModeTwoFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+  prof_end(kProfTwoFilterUp, a.stream);
+  MS_CHECK(hipGetLastError());
+  TrajOut to{a.S, a.v, a.xs, a.Ps, 0, 0};
+  prof_begin(kProfTwoFilterDown, a.stream);
+  if (a.Ps != nullptr)
+    k_two_filter_down<TS, T, M, true><<<g, kBlock, 0, a.stream>>>(p, w, to);
+  else
+    k_two_filter_down<TS, T, M, false><<<g, kBlock, 0, a.stream>>>(p, w, to);
+  prof_end(kProfTwoFilterDown, a.stream);
+  return hipGetLastError();
+}
+
 #define MS_COMMA ,
 #define MS_INSTANTIATE(M)                 \
   template struct Runner<double, double, M>; \
