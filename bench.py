@@ -75,7 +75,39 @@ def kernel_bytes(nx, ny, s, kind):
         "fused_down": (ny + sym + nx) * s,                # read y, write S, v
         "traj_down": (sym + nx + ny + nx + sym) * s,      # read S, v, y; write xs, Ps
         "traj_down_adjoint": (sym + nx + ny + nx + sym) * s,
+        "two_filter_up": (ny + sym + nx) * s,             # read y, write S, v
+        "two_filter_down": (sym + nx + ny + nx + sym) * s,  # read S, v, y; write xs, Ps
     }[kind]
+
+
+def roofline_for(kern, rec, fresh, n_states, nx, ny, s, dtype):
+    """Roofline object of the longest kernel in `kern` {name: (count, ms)}:
+    against the FP64 VALU roof when the counter record has its flop count on
+    this workload, else against HBM with its algorithmic bytes."""
+    dom = max((k for k in kern if k != "aux"), key=lambda k: kern[k][1])
+    dom_ms = kern[dom][1]
+    bytes_dom = kernel_bytes(nx, ny, s, dom) * n_states
+    hbm_gbs = bytes_dom / (dom_ms * 1e-3) / 1e9
+    kc = (rec or {}).get("kernels", {}).get(dom)
+    if kc is not None and kc.get("n_states") == n_states:
+        # FP64 VALU roof: the per-state flop count of the kernel (counted, see
+        # the counter record) over its measured launch duration
+        flops = kc["flops_fp64_per_state"] * n_states
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS[dtype], 4),
+                "traffic": kc["hbm_bytes"] if fresh else None,
+                "flops_per_state": kc["flops_fp64_per_state"],
+                "counters_current": fresh}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roof.update({
+        "kernel": dom, "kernel_ms": round(dom_ms, 4),
+        "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
+        "hbm_algorithmic": {"bytes": bytes_dom, "achieved_GBs": round(hbm_gbs, 1),
+                            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}})
+    return roof
 
 
 def main():
@@ -88,9 +120,13 @@ def main():
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6144)
+    ap.add_argument("--cpu-sample-tf", type=int, default=2 ** 20,
+                    help="steps of the two-filter CPU-baseline sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default schedule instead of autotuning it")
+    ap.add_argument("--no-two-filter", action="store_true",
+                    help="skip the two-filter smoother measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -116,7 +152,10 @@ def main():
                       seed=2, name="cfg2_cv2d")
     p = ms.problem_from_workload(wl, dtype=tdt, device=dev)
     # schedule (states per lane) picked by the library's autotuner, untimed
-    chunk = None if args.no_autotune else ms.autotune(p)
+    tuned = not args.no_autotune
+    if tuned:
+        ms.autotune(p)
+    chunk = ms.schedule(p)
     nsym = p.nsym
     out = dict(S=p._tiled(nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx), Ps=p._tiled(nsym),
                loglik=p._empty(1, dtype=torch.float64), obj=p._empty(1, dtype=torch.float64),
@@ -173,33 +212,33 @@ def main():
         ms_pl, _, _ = timed(g_pl.replay, args.steps, args.warmup, False)
 
     s = 8 if args.dtype == "f64" else 4
-    # dominant kernel of the fwd+adjoint step
-    dom = max((k for k in kern_fa if k != "aux"), key=lambda k: kern_fa[k][1])
-    dom_ms = kern_fa[dom][1]
-    bytes_dom = kernel_bytes(p.nx, p.ny, s, dom) * p.n_states
-    hbm_gbs = bytes_dom / (dom_ms * 1e-3) / 1e9
     step_bytes = (p.ny + 2 * (nsym + p.nx) + p.nx + nsym) * s * p.n_states
     rec, fresh = counter_record(args.dtype)
-    kc = (rec or {}).get("kernels", {}).get(dom)
-    if kc is not None and kc.get("n_states") == p.n_states:
-        # FP64 VALU roof: the per-state flop count of the kernel (counted, see
-        # the counter record) over its measured launch duration
-        flops = kc["flops_fp64_per_state"] * p.n_states
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],
-                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS[args.dtype], 4),
-                    "traffic": kc["hbm_bytes"] if fresh else None,
-                    "flops_per_state": kc["flops_fp64_per_state"],
-                    "counters_current": fresh}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    roofline.update({
-        "kernel": dom, "kernel_ms": round(dom_ms, 4),
-        "kernels_ms": {k: round(v[1], 4) for k, v in kern_fa.items()},
-        "hbm_algorithmic": {"bytes": bytes_dom, "achieved_GBs": round(hbm_gbs, 1),
-                            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)},
-        "step_hbm_frac": round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    # dominant kernel of the fwd+adjoint step
+    roofline = roofline_for(kern_fa, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)
+    roofline["step_hbm_frac"] = round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    two_filter = None
+    if not args.no_two_filter:
+        # the two-filter smoother (Sec. 4.3) on the same workload: x*, P^s and
+        # the log-likelihood (it has no objective or adjoint)
+        tf_out = dict(S=out["S"], v=out["v"], xs=out["xs"], Ps=out["Ps"], loglik=out["loglik"])
+
+        def step_tf():
+            ms.two_filter_smooth(p, covariances=True, loglik=True, out=tf_out, natural=False)
+
+        ms_tf_e, _, kern_tf = timed(step_tf, args.steps, args.warmup, True)
+        if args.no_graph:
+            ms_tf = ms_tf_e
+        else:
+            g_tf = ms.GraphedSmooth(p, covariances=True, loglik=True, objective=False, grad=False,
+                                    form="two_filter")
+            ms_tf, _, _ = timed(g_tf.replay, args.steps, args.warmup, False)
+        two_filter = {"value": T / (ms_tf * 1e-3), "unit": "time-steps/s", "ms_per_step": ms_tf,
+                      "eager_ms_per_step": round(ms_tf_e, 4),
+                      "outputs": "filter S, v; smoothed x*, P^s; log-likelihood",
+                      "roofline": roofline_for(kern_tf, rec, fresh, p.n_states, p.nx, p.ny, s,
+                                               args.dtype)}
 
     res = {
         "metric": METRIC,
@@ -218,7 +257,7 @@ def main():
                                "r=0.05, one trajectory; filter + smoother (x*, P^s) + log-lik + "
                                "objective + adjoint d/d(gamma,q,r)" % args.log2T,
                    "T": T, "nx": 4, "ny": 2, "n_seg": 1, "storage": args.dtype,
-                   "schedule": {"states_per_lane": chunk, "autotuned": chunk is not None}},
+                   "schedule": {"states_per_lane": chunk, "autotuned": tuned}},
         "plain_scan": {"value": T / (ms_pl * 1e-3), "ms_per_step": ms_pl,
                        "kernels_ms": {k: round(v[1], 4) for k, v in kern_pl.items()}},
         "wall_ms_per_step": round(wall_fa, 4),
@@ -226,6 +265,8 @@ def main():
         "eager_ms_per_step": {"fwd_adjoint": round(ms_fa_e, 4), "plain": round(ms_pl_e, 4)},
         "roofline": roofline,
     }
+    if two_filter is not None:
+        res["two_filter"] = two_filter
 
     if args.copy_calibration:
         # plain device-to-device copy of a known size, read and written once,
@@ -241,6 +282,8 @@ def main():
         res["flop_calibration_fp64"] = 1 << 24
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+        if two_filter is not None:
+            two_filter["cpu_baseline"] = cpu_baseline_two_filter(wl, args.cpu_sample_tf)
     print(json.dumps(res))
 
 
@@ -267,6 +310,35 @@ def cpu_baseline(wl, n):
                       "smoother + log-likelihood + objective, gradients by autograd, FP64, "
                       "%.1f s" % (n, dt),
             "cpu": cpu_info()}
+
+
+def cpu_baseline_two_filter(wl, n):
+    """The plain-C sequential oracle of the two-filter smoother (covariance
+    Kalman filter, then the later-step runs by the combination rule and one
+    joint solve per state) on the first n steps of the same trajectory, one
+    thread."""
+    from oracle import cref
+
+    sub = workloads_prefix(wl, n)
+    t0 = time.perf_counter()
+    cref.two_filter(sub)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the same trajectory: sequential C two-filter smoother "
+                      "(filter, later-step runs, per-state joint solve), FP64, %.1f s" % (n, dt),
+            "cpu": cpu_info()}
+
+
+def workloads_prefix(wl, n):
+    import workloads
+
+    sub = workloads.Workload(**{**wl.__dict__})
+    sub.seg_off = wl.seg_off.copy()
+    sub.seg_off[-1] = n
+    sub.dt = wl.dt[:n]
+    sub.y = wl.y[:, :n]
+    sub.x_true = wl.x_true[:, :n + 1]
+    return sub
 
 
 if __name__ == "__main__":

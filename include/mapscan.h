@@ -237,6 +237,11 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
 map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,
                         int32_t* chunk_out, void* stream);
 
+/* The schedule (states per lane: 4, 8 or 16) the scan entry points use for
+ * this problem: p->chunk if set, else the choice map_autotune recorded for
+ * its shape, else the library's heuristic.  Host-only; launches nothing. */
+map_status map_schedule(const map_problem* p, int32_t* chunk_out);
+
 /* Measurement hook (no effect on results).  map_profile_enable(n) creates n
  * pairs of HIP events (0 disables and releases them); while enabled, each
  * kernel the library launches is bracketed by one pair recorded on its

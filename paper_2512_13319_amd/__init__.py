@@ -26,7 +26,7 @@ from . import _lib
 from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
-           "two_filter_smooth",
+           "two_filter_smooth", "autotune", "schedule",
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
            "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
@@ -255,6 +255,14 @@ def autotune(p: Problem, cache_path=None) -> int:
     return int(out.value)
 
 
+def schedule(p: Problem) -> int:
+    """States per lane the scan entry points use for this problem."""
+    lib = _lib.load()
+    out = ctypes.c_int32(0)
+    _lib.check(lib.map_schedule(ctypes.byref(p.struct), ctypes.byref(out)))
+    return int(out.value)
+
+
 def build_elements(p: Problem, natural=True):
     """Elements of every state as [A (nx*nx), b, C (sym), eta, J (sym)] components."""
     lib = _lib.load()
@@ -377,16 +385,21 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True):
 
 
 class GraphedSmooth:
-    """The fused launch sequence of `smooth` captured once into a HIP graph
-    (torch.cuda.CUDAGraph on ROCm) with fixed output buffers, then replayed.
-    Inputs are read from the Problem's device buffers at replay time, so
-    refreshing their contents in place (same shapes) is seen by the next
-    replay.  The sequence contains kernel launches only (the accumulators are
-    cleared by a kernel, not by memset nodes)."""
+    """A launch sequence of `smooth` (form "rts") or of `two_filter_smooth`
+    (form "two_filter") captured once into a HIP graph (torch.cuda.CUDAGraph
+    on ROCm) with fixed output buffers, then replayed.  Inputs are read from
+    the Problem's device buffers at replay time, so refreshing their contents
+    in place (same shapes) is seen by the next replay.  The sequence contains
+    kernel launches only (the accumulators are cleared by a kernel, not by
+    memset nodes)."""
 
-    def __init__(self, p: Problem, covariances=True, loglik=True, objective=True, grad=False):
+    def __init__(self, p: Problem, covariances=True, loglik=True, objective=True, grad=False,
+                 form="rts"):
+        if form not in ("rts", "two_filter"):
+            raise ValueError("form must be 'rts' or 'two_filter'")
+        if form == "two_filter" and (objective or grad):
+            raise ValueError("the two-filter form has no objective or gradients")
         self.p = p
-        self.kw = dict(covariances=covariances, loglik=loglik, objective=objective, grad=grad)
         f64 = torch.float64
         self.out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx),
                         Ps=p._tiled(p.nsym) if covariances else None,
@@ -394,16 +407,25 @@ class GraphedSmooth:
                         obj=p._empty(p.n_seg, dtype=f64) if objective else None,
                         g_loglik=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None,
                         g_obj=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None)
+        if form == "rts":
+            kw = dict(covariances=covariances, loglik=loglik, objective=objective, grad=grad)
+
+            def run():
+                smooth(p, out=self.out, natural=False, **kw)
+        else:
+            def run():
+                two_filter_smooth(p, covariances=covariances, loglik=loglik, out=self.out,
+                                  natural=False)
         p.workspace()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            smooth(p, out=self.out, natural=False, **self.kw)   # warm-up outside capture
+            run()   # warm-up outside capture
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            smooth(p, out=self.out, natural=False, **self.kw)
+            run()
 
     def replay(self):
         self.graph.replay()

@@ -510,6 +510,14 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
   return MAP_OK;
 }
 
+map_status map_schedule(const map_problem* p, int32_t* chunk_out) {
+  map_status s = validate(p, false);
+  if (s != MAP_OK) return s;
+  if (chunk_out == nullptr) return fail(MAP_E_ARG, "chunk_out is NULL");
+  *chunk_out = sched::resolve(*p);
+  return MAP_OK;
+}
+
 map_status map_profile_enable(int32_t capacity) {
   for (auto& r : prof::g_recs) {
     hipEventDestroy(r.a);

@@ -207,3 +207,22 @@ def test_nonlinear_model_needs_xbar():
     assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                None) == -1
     assert b"xbar" in lib.map_last_error()
+
+
+def test_schedule_query():
+    """map_schedule: the problem's own chunk when set; otherwise the library's
+    choice, which is always one of the three schedules."""
+    lib = _lib.load()
+    out = ctypes.c_int32(0)
+    big = np.array([0, 5000, 12000], dtype=np.int64)
+    for c in (4, 8, 16):
+        p = good(big)
+        p.chunk = c
+        assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == 0
+        assert out.value == c
+    p = good(big)
+    assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == 0
+    assert out.value in (4, 8, 16)
+    assert lib.map_schedule(ctypes.byref(p), None) == -1
+    p.chunk = 3
+    assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == -1
