@@ -67,12 +67,17 @@ def _terms(wl, xbar):
     F = np.empty((N, nx, nx)); c = np.empty((N, nx)); H = np.empty((N, ny, nx))
     r = np.empty((N, ny)); Wm = np.empty((S, nw, nw)); R = np.empty((S, ny, ny))
     L = None
+    Ls = []
     for s in range(S):
         st = wl.seg_steps(s)
         xb = xbar[:, st.start + s + 1: st.stop + s + 1].T
-        F_, c_, L, W_, H_, r_, R_ = models.terms_numpy(wl.model, wl.theta[s], xb, nx)
+        F_, c_, L, W_, H_, r_, R_ = models.terms_numpy(wl.model, wl.theta[s], xb, nx,
+                                                       wl.y[:, st].T)
+        Ls.append(L)
         F[st], c[st], H[st], r[st], Wm[s], R[s] = F_, c_, H_, r_, W_, R_
-    return dict(F=(F, nx * nx, 0), c=(c, nx, 0), L=(np.ascontiguousarray(L), 0, 0),
+    # L may depend on the segment's parameters (ct)
+    Lall = np.ascontiguousarray(np.stack(Ls))
+    return dict(F=(F, nx * nx, 0), c=(c, nx, 0), L=(Lall, 0, nx * nw),
                 W=(Wm, 0, nw * nw), H=(H, ny * nx, 0), r=(r, ny, 0), R=(R, 0, ny * ny))
 
 

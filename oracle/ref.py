@@ -117,6 +117,8 @@ def map_objective_nonlinear(model, theta, x, dt, y, m0, P0, nx):
         h = dt[k - 1]
         u = Lp @ (x[k] - x[k - 1] - h * f[k - 1])
         eps = y[k - 1] - hx[k - 1]
+        if model == "ct":
+            eps = torch.stack([eps[0], models.wrap_angle(eps[1])])
         M = M + 0.5 * u @ Winv @ u / h + 0.5 * h * eps @ Rinv @ eps
     return M
 
@@ -128,7 +130,7 @@ def smooth_segment(model, theta, xbar, dt, y, m0, P0, nx, lin=None):
     if lin is not None:
         F, c, L, W, H, r, R = (lin[k] for k in ("F", "c", "L", "W", "H", "r", "R"))
     else:
-        F, c, L, W, H, r, R = models.terms_torch(model, theta, xbar[1:], nx)
+        F, c, L, W, H, r, R = models.terms_torch(model, theta, xbar[1:], nx, y)
     m, P, mp, Pp, ll = kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0)
     xs, Ps = rts_smoother(F, dt, m, P, mp, Pp)
     M = map_objective(xs, F, c, L, W, H, r, R, dt, y, m0, P0)

@@ -349,3 +349,143 @@ def test_two_filter_end_state_is_filter():
     assert not o["suf"]["J"][last].any() and not o["suf"]["C"][last].any()
     assert np.abs(o["xs"][last] - o["m"][last]).max() <= 1e-12 * np.abs(o["m"][last]).max()
     assert np.abs(o["Ps"][last] - o["P"][last]).max() <= 1e-12 * np.abs(o["P"][last]).max()
+
+
+# ------------------------------------------------------------------ coordinated turn (Sec. 5.2)
+from oracle import models as _models
+
+
+def test_ct_drift_is_a_coordinated_turn():
+    """With the turn rate held and no noise the drift moves the target on a
+    circle at constant speed: velocity rotated by omega t, position
+    p0 + (sin(w t) v0 + (1 - cos(w t)) J v0) / w with J the +90 degree rotation.
+    RK4 on the oracle's drift against that closed form."""
+    th = torch.tensor([5e-4, 0.02, 5e-3, 1e-3], dtype=torch.float64)
+    x0 = torch.tensor([[5.0, 5.0, 0.2, 0.3, 0.35]], dtype=torch.float64)
+    f = lambda x: _models.drift_torch("ct", th, x, 5)[0]
+    h, n = 1e-3, 4000
+    x = x0.clone()
+    for _ in range(n):
+        k1 = f(x); k2 = f(x + 0.5 * h * k1); k3 = f(x + 0.5 * h * k2); k4 = f(x + h * k3)
+        x = x + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    t, w = n * h, 0.35
+    v0 = np.array([0.2, 0.3])
+    Jv0 = np.array([-0.3, 0.2])
+    v = np.cos(w * t) * v0 + np.sin(w * t) * Jv0
+    p = np.array([5.0, 5.0]) + (np.sin(w * t) * v0 + (1 - np.cos(w * t)) * Jv0) / w
+    assert np.abs(x[0, :2].numpy() - p).max() < 1e-11
+    assert np.abs(x[0, 2:4].numpy() - v).max() < 1e-11
+    assert x[0, 4].item() == 0.35
+
+
+def test_ct_measurement_at_known_points():
+    th = torch.tensor([5e-4, 0.02, 5e-3, 1e-3], dtype=torch.float64)
+    pts = torch.tensor([[3.0, 4.0, 0, 0, 0], [-1.0, 0.0, 0, 0, 0], [0.0, -2.0, 0, 0, 0],
+                        [-1.0, -1.0, 0, 0, 0]], dtype=torch.float64)
+    _, hx = _models.drift_torch("ct", th, pts, 5)
+    want = np.array([[5.0, np.arctan(4.0 / 3.0)], [1.0, np.pi], [2.0, -np.pi / 2],
+                     [np.sqrt(2.0), -3 * np.pi / 4]])
+    assert np.abs(hx.numpy() - want).max() < 1e-15
+    e = np.array([0.1, np.pi - 1e-9, -np.pi, np.pi, 7.0, -7.0])
+    w = _models.wrap_angle(e)
+    assert np.all(w >= -np.pi) and np.all(w < np.pi)
+    assert np.abs(np.sin(w) - np.sin(e)).max() < 1e-14 and np.abs(np.cos(w) - np.cos(e)).max() < 1e-14
+
+
+def test_ct_taylor_terms_match_finite_differences():
+    """F = df/dx, H = dh/dx at xbar by central differences of the drift and
+    measurement; c, r make the expansion exact at xbar."""
+    rng = np.random.default_rng(3)
+    xb = np.column_stack([rng.uniform(2, 8, 6), rng.uniform(-8, 8, 6), rng.normal(0, 0.5, 6),
+                          rng.normal(0, 0.5, 6), rng.normal(0, 0.3, 6)])
+    th = np.array([5e-4, 0.02, 5e-3, 1e-3])
+    F, c, L, W, H, r, R = _models.terms_numpy("ct", th, xb, 5)
+    tt = torch.tensor(th)
+
+    def fh(x):
+        f, hx = _models.drift_torch("ct", tt, torch.tensor(x), 5)
+        return f.numpy(), hx.numpy()
+    eps = 1e-6
+    for j in range(5):
+        dp = xb.copy(); dp[:, j] += eps
+        dm = xb.copy(); dm[:, j] -= eps
+        (fp, hp), (fm, hm) = fh(dp), fh(dm)
+        assert np.abs((fp - fm) / (2 * eps) - F[:, :, j]).max() < 1e-8
+        assert np.abs((hp - hm) / (2 * eps) - H[:, :, j]).max() < 1e-8
+    f0, h0 = fh(xb)
+    assert np.abs(np.einsum("kij,kj->ki", F, xb) + c - f0).max() < 1e-14
+    assert np.abs(np.einsum("kij,kj->ki", H, xb) + r - h0).max() < 1e-13
+    assert np.allclose(L @ W @ L.T, np.diag([0, 0, th[0] ** 2, th[0] ** 2, th[1] ** 2]))
+
+
+def test_ct_bearing_shift_by_two_pi_changes_nothing():
+    wl = workloads.ct(n_seg=2, T=300, seed=81)
+    xb = np.ascontiguousarray(wl.x_true)
+    a = cref.smooth(wl, xb)
+    w2 = workloads.Workload(**{**wl.__dict__})
+    w2.y = wl.y.copy()
+    k = np.arange(0, w2.y.shape[1], 7)
+    w2.y[1, k] += 2 * np.pi * np.where(k % 2 == 0, 1.0, -1.0)
+    b = cref.smooth(w2, xb)
+    for key in ("xs", "Ps", "m", "P"):
+        assert np.abs(a[key] - b[key]).max() <= 1e-11 * np.abs(a[key]).max()
+    assert np.abs(a["loglik"] - b["loglik"]).max() <= 1e-11 * np.abs(a["loglik"]).max()
+
+
+def test_ct_gauss_newton_matches_constrained_least_squares():
+    """Gauss--Newton (Sec. 4.4) on the coordinated-turn model converges to the
+    minimiser of the nonlinear discretised objective.  Q is singular (the
+    position rows of L are zero), so the least-squares problem is written in
+    the free variables: x_0 and, per step, the velocity and turn rate; the
+    positions follow from xi_k = xi_{k-1} + dt dxi_k (the noise-free rows of
+    the implicit-Euler step)."""
+    wl = workloads.ct(n_seg=1, T=40, dt=0.05, seed=82, n_iter=14)
+    o = cref.iterate(wl)
+    sv, sw, r1, r2 = wl.theta[0]
+    T, dt = wl.n_steps, wl.dt[0]
+    y = wl.y
+    P0i = np.linalg.cholesky(np.linalg.inv(wl.P0[0])).T
+
+    def states(z):
+        x0 = z[:5]
+        vw = z[5:].reshape(T, 3)
+        pos = x0[:2] + dt * np.cumsum(vw[:, :2], 0)
+        xs = np.column_stack([pos, vw])
+        return np.vstack([x0, xs])
+
+    def resid(z):
+        x = states(z)
+        v, om = x[:, 2:4], x[:, 4]
+        fv = np.column_stack([-om[1:] * v[1:, 1], om[1:] * v[1:, 0]])
+        Dv = (v[1:] - v[:-1] - dt * fv) / (np.sqrt(dt) * sv)
+        Dw = (om[1:] - om[:-1]) / (np.sqrt(dt) * sw)
+        hr = np.hypot(x[1:, 0], x[1:, 1])
+        hb = np.arctan2(x[1:, 1], x[1:, 0])
+        eb = y[1] - hb
+        eb = eb - 2 * np.pi * np.floor(eb / (2 * np.pi) + 0.5)
+        E = np.concatenate([(y[0] - hr) * np.sqrt(dt / r1), eb * np.sqrt(dt / r2)])
+        return np.concatenate([P0i @ (x[0] - wl.m0[0]), Dv.reshape(-1), Dw, E])
+
+    xg = o["xs"]
+    z0 = np.concatenate([xg[0], xg[1:, 2:].reshape(-1)])
+    sol = scipy.optimize.least_squares(resid, z0 + 1e-3, xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    x_ls = states(sol.x)
+    assert np.abs(xg - x_ls).max() < 1e-7 * np.abs(x_ls).max()
+    # the positions of the Gauss--Newton solution obey the noise-free rows
+    assert np.abs(xg[1:, :2] - xg[:-1, :2] - dt * xg[1:, 2:4]).max() < 1e-12
+
+
+def test_ct_iterates_c_and_torch_agree_and_decrease():
+    wl = workloads.ct(n_seg=2, T=150, dt=0.02, seed=83, n_iter=5)
+    o = cref.iterate(wl, keep_iterates=True)
+    for s in range(2):
+        seg = ref.workload_segment(wl, s)
+        its, _ = ref.gauss_newton("ct", seg["theta"], seg["dt"], seg["y"], seg["m0"], seg["P0"],
+                                  5, 5)
+        st = wl.seg_states(s)
+        for i in range(5):
+            np.testing.assert_allclose(o["iterates"][i][:, st].T, its[i].numpy(), rtol=0,
+                                       atol=1e-9 * np.abs(its[i].numpy()).max())
+        obj = [ref.map_objective_nonlinear("ct", seg["theta"], x, seg["dt"], seg["y"], seg["m0"],
+                                           seg["P0"], 5).item() for x in its]
+        assert all(b <= a + 1e-9 * abs(a) for a, b in zip(obj[1:], obj[2:]))

@@ -31,14 +31,14 @@ import dataclasses
 import numpy as np
 from scipy.signal import lfilter
 
-MODEL_IDS = {"linear": 0, "cv": 1, "vdp": 2, "lorenz63": 3}
-N_THETA = {"cv": 3, "vdp": 3, "lorenz63": 5}
+MODEL_IDS = {"linear": 0, "cv": 1, "vdp": 2, "lorenz63": 3, "ct": 4}
+N_THETA = {"cv": 3, "vdp": 3, "lorenz63": 5, "ct": 4}
 
 
 @dataclasses.dataclass
 class Workload:
     name: str
-    model: str                 # "cv" | "vdp" | "lorenz63" | "linear"
+    model: str                 # "cv" | "vdp" | "lorenz63" | "ct" | "linear"
     nx: int
     ny: int
     nw: int
@@ -218,6 +218,46 @@ def lorenz63(n_seg=256, T=2 ** 14, dt=1e-3, sigma=10.0, rho=28.0, beta=8.0 / 3.0
         y[:, s * T:(s + 1) * T] = _measure(rng, X[s][:, 1:], dt, r)
     theta = np.tile(np.array([sigma, rho, beta, q, r]), (n_seg, 1))
     return Workload(name=name, model="lorenz63", nx=3, ny=3, nw=3, seg_off=seg_off,
+                    dt=np.full(n_seg * T, dt), y=y, theta=theta,
+                    m0=np.tile(m0, (n_seg, 1)), P0=np.tile(P0m, (n_seg, 1, 1)), x_true=xs,
+                    n_iter=n_iter)
+
+
+def ct(n_seg=64, T=2 ** 14, dt=1e-3, sv=5e-4, sw=0.02, r=(5e-3, 1e-3),
+       m0=(5.0, 5.0, 0.0, 0.3, 0.0), P0=(0.01, 0.01, 0.01, 0.01, 0.04), n_iter=5, seed=6,
+       name="ct") -> Workload:
+    """Coordinated-turn tracks with the parameters of the paper's nonlinear
+    experiment (Sec. 5.2): x = (xi, zeta, dxi, dzeta, omega), turn rate a random
+    walk with spectral density sw^2, velocity rotated at the turn rate plus
+    white acceleration with density sv^2, range and bearing measured with
+    spectral densities r (per-sample covariance r/dt), bearings reported in
+    [-pi, pi).  The velocity is simulated with an exponential integrator of the
+    rotation: with z = dxi + i dzeta and phase Phi_k = dt sum_{j<k} omega_j,
+    z_k = exp(i Phi_k) (z_0 + sum_{j<k} exp(-i Phi_{j+1}) sv dB_j); position is
+    the running sum of dt z."""
+    rng = _rng(seed)
+    m0 = np.asarray(m0, dtype=np.float64)
+    P0m = np.diag(np.asarray(P0, dtype=np.float64))
+    seg_off = np.arange(n_seg + 1, dtype=np.int64) * T
+    y = np.empty((2, n_seg * T))
+    xs = np.empty((5, n_seg * (T + 1)))
+    for s in range(n_seg):
+        x0 = rng.multivariate_normal(m0, P0m)
+        om = x0[4] + np.concatenate([[0.0], np.cumsum(rng.standard_normal(T) * sw * np.sqrt(dt))])
+        phase = np.concatenate([[0.0], np.cumsum(om[:-1] * dt)])           # Phi_0..Phi_T
+        dB = (rng.standard_normal(T) + 1j * rng.standard_normal(T)) * sv * np.sqrt(dt)
+        acc = np.concatenate([[0.0], np.cumsum(np.exp(-1j * phase[1:]) * dB)])
+        z = np.exp(1j * phase) * (x0[2] + 1j * x0[3] + acc)
+        p = (x0[0] + 1j * x0[1]) + np.concatenate([[0.0], np.cumsum(z[1:] * dt)])
+        X = np.stack([p.real, p.imag, z.real, z.imag, om])
+        xs[:, s * (T + 1):(s + 1) * (T + 1)] = X
+        rng_ = np.hypot(X[0, 1:], X[1, 1:])
+        brg = np.arctan2(X[1, 1:], X[0, 1:])
+        yy = _measure(rng, np.stack([rng_, brg]), dt, np.asarray(r, dtype=np.float64)[:, None])
+        yy[1] = yy[1] - 2.0 * np.pi * np.floor(yy[1] / (2.0 * np.pi) + 0.5)
+        y[:, s * T:(s + 1) * T] = yy
+    theta = np.tile(np.array([sv, sw, r[0], r[1]]), (n_seg, 1))
+    return Workload(name=name, model="ct", nx=5, ny=2, nw=3, seg_off=seg_off,
                     dt=np.full(n_seg * T, dt), y=y, theta=theta,
                     m0=np.tile(m0, (n_seg, 1)), P0=np.tile(P0m, (n_seg, 1, 1)), x_true=xs,
                     n_iter=n_iter)
