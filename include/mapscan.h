@@ -99,12 +99,20 @@ typedef enum { MAP_F32 = 0, MAP_F64 = 1, MAP_F32_FAST = 2 } map_dtype;
  *                       h = x1, R = r; nx = 2, ny = 1, nw = 2.
  *   MAP_MODEL_LORENZ63  (sigma, rho, beta, q, r): Lorenz-63 drift, L = I, W = q I,
  *                       h = x, R = r I; nx = ny = nw = 3.
- * Nonlinear models (VDP, LORENZ63) are linearised about map_problem.xbar. */
+ *   MAP_MODEL_CT        (sv, sw, r1, r2): coordinated turn (Sec. 5.2), state
+ *                       (xi, zeta, dxi, dzeta, omega), f = (dxi, dzeta, -omega dzeta,
+ *                       omega dxi, 0), L = [[0,0,0],[0,0,0],[sv,0,0],[0,sv,0],[0,0,sw]],
+ *                       W = I, h = (sqrt(xi^2 + zeta^2), atan2(zeta, xi)),
+ *                       R = diag(r1, r2); nx = 5, ny = 2, nw = 3.  Bearings are in
+ *                       radians; the bearing residual is taken modulo 2 pi into
+ *                       [-pi, pi), so measurements may be given on any branch.
+ * Nonlinear models (VDP, LORENZ63, CT) are linearised about map_problem.xbar. */
 typedef enum {
   MAP_MODEL_LINEAR = 0,
   MAP_MODEL_CV = 1,
   MAP_MODEL_VDP = 2,
-  MAP_MODEL_LORENZ63 = 3
+  MAP_MODEL_LORENZ63 = 3,
+  MAP_MODEL_CT = 4
 } map_model;
 
 typedef struct {

@@ -30,7 +30,7 @@ __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
            "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
-N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5}
+N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5, "ct": 4}
 TILE = 1024      # states per tile: 64 lanes x 16 states
 LANES, CHUNK = 64, 16
 
@@ -95,7 +95,7 @@ def sym_to_full(planes: torch.Tensor, nx: int) -> torch.Tensor:
 class Problem:
     """A batch of trajectories of one model, resident on the GPU.
 
-    model     "cv" | "vdp" | "lorenz63" | "linear"
+    model     "cv" | "vdp" | "lorenz63" | "ct" | "linear"
     seg_off   int64 [n_seg+1] step offsets (host array or tensor)
     dt        [n_steps] step lengths (or a 0-d tensor / float for a shared value)
     y         [ny, n_steps] measurements

@@ -414,6 +414,12 @@ struct Cursor {
         for (int c = 0; c < NX; ++c) xb[c] = T(0);
       }
       M::terms(th, xb, dt, st);
+      if constexpr (M::kAngle >= 0) {
+        // angular component: the residual y - r modulo 2 pi into [-pi, pi),
+        // i.e. the measurement taken on the branch nearest the prediction
+        constexpr int a = M::kAngle;
+        st.r[a] = r.y[a] - wrap_angle(r.y[a] - st.r[a]);
+      }
     } else {
       st.dt = dt;
       const TS* F = p.F + k * p.sF;

@@ -82,6 +82,21 @@ template <> MS_DEV void sqrt_rsqrt<float>(float x, float& d, float& di) {
   di = 1.0f / d;
 #endif
 }
+template <typename T> MS_DEV T atan2_(T y, T x);
+template <> MS_DEV double atan2_<double>(double y, double x) { return ::atan2(y, x); }
+template <> MS_DEV float atan2_<float>(float y, float x) { return ::atan2f(y, x); }
+template <typename T> MS_DEV T floor_(T x);
+template <> MS_DEV double floor_<double>(double x) { return __builtin_floor(x); }
+template <> MS_DEV float floor_<float>(float x) { return __builtin_floorf(x); }
+
+// e modulo 2 pi into [-pi, pi): e - 2 pi floor(e / (2 pi) + 1/2)
+template <typename T>
+MS_DEV T wrap_angle(T e) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+  return e - T(kTwoPi) * floor_(e * T(kInvTwoPi) + T(0.5));
+}
+
 template <typename T> MS_DEV T log_(T x);
 template <> MS_DEV double log_<double>(double x) { return ::log(x); }
 template <> MS_DEV float log_<float>(float x) { return ::logf(x); }

@@ -78,6 +78,7 @@ struct Entry {
   X(MAP_MODEL_CV, 6, 3, 3, 3, ModelCV<3>)         \
   X(MAP_MODEL_VDP, 2, 1, 2, 3, ModelVdP)          \
   X(MAP_MODEL_LORENZ63, 3, 3, 3, 5, ModelLorenz63) \
+  X(MAP_MODEL_CT, 5, 2, 3, 4, ModelCT)            \
   X(MAP_MODEL_LINEAR, 1, 1, 1, 0, ModelLinear<1 MS_COMMA 1 MS_COMMA 1>) \
   X(MAP_MODEL_LINEAR, 2, 1, 1, 0, ModelLinear<2 MS_COMMA 1 MS_COMMA 1>) \
   X(MAP_MODEL_LINEAR, 2, 1, 2, 0, ModelLinear<2 MS_COMMA 1 MS_COMMA 2>) \
@@ -113,7 +114,9 @@ int model_ntheta(const map_problem& p) {
   return -1;
 }
 
-bool model_nonlinear(int model) { return model == MAP_MODEL_VDP || model == MAP_MODEL_LORENZ63; }
+bool model_nonlinear(int model) {
+  return model == MAP_MODEL_VDP || model == MAP_MODEL_LORENZ63 || model == MAP_MODEL_CT;
+}
 
 map_status validate(const map_problem* pp, bool need_xbar = true) {
   if (pp == nullptr) return fail(MAP_E_ARG, "problem is NULL");
@@ -122,7 +125,7 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
     return fail(MAP_E_DTYPE, "unknown dtype %d", p.dtype);
   if (p.nx < 1 || p.nx > 8 || p.ny < 1 || p.ny > 8 || p.nw < 1 || p.nw > 8)
     return fail(MAP_E_DIM, "dimensions (nx, ny, nw) = (%d, %d, %d) outside [1, 8]", p.nx, p.ny, p.nw);
-  if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_LORENZ63)
+  if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_CT)
     return fail(MAP_E_ARG, "unknown model %d", p.model);
   if (p.chunk != 0 && !valid_chunk(p.chunk))
     return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8 or 16", p.chunk);

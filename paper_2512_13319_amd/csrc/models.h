@@ -59,6 +59,7 @@ struct ModelCV {
   static constexpr int NX = 2 * D, NY = D, NW = D, NTH = 3;
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = true;
+  static constexpr int kAngle = -1;  // no angular measurement component
 
   template <typename T>
   static MS_DEV void terms(const T* th, const T (&)[NX], T dt, Step<T, NX, NY, NW>& s) {
@@ -111,6 +112,7 @@ struct ModelVdP {
   static constexpr int NX = 2, NY = 1, NW = 2, NTH = 3;
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
+  static constexpr int kAngle = -1;
 
   template <typename T>
   static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {
@@ -159,6 +161,7 @@ struct ModelLorenz63 {
   static constexpr int NX = 3, NY = 3, NW = 3, NTH = 5;
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
+  static constexpr int kAngle = -1;
 
   template <typename T>
   static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {
@@ -212,6 +215,81 @@ struct ModelLinear {
   static constexpr int NX = NX_, NY = NY_, NW = NW_, NTH = 0;
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = false;
+  static constexpr int kAngle = -1;
+};
+
+// ------------------------------------------------------------------ coordinated turn
+// The nonlinear model of Sec. 5.2: x = (xi, zeta, dxi, dzeta, omega),
+// f = (dxi, dzeta, -omega dzeta, omega dxi, 0), L = [[0,0,0],[0,0,0],[sv,0,0],
+// [0,sv,0],[0,0,sw]], W = I, h = (sqrt(xi^2 + zeta^2), atan2(zeta, xi)) (the
+// paper's arctan(zeta / xi), continued to every direction), R = diag(r1, r2);
+// theta = (sv, sw, r1, r2).  Taylor terms at xbar:
+//   F rows 2, 3: (0, 0, 0, -omega, -dzeta), (0, 0, omega, 0, dxi);  c = (0, 0, omega dzeta, -omega dxi, 0)
+//   H = [[xi/rho, zeta/rho, 0, 0, 0], [-zeta/rho^2, xi/rho^2, 0, 0, 0]],  r = (0, atan2(zeta, xi))
+// (H xbar reproduces the range exactly and has no bearing part).  Measurement
+// component kAngle is a bearing: its residual y - r is taken modulo 2 pi into
+// [-pi, pi) (done where the step's measurement is read, see Cursor::terms).
+// Q = L L^T is singular; C = dt Q keeps the factor V = sqrt(dt) L.
+struct ModelCT {
+  static constexpr int NX = 5, NY = 2, NW = 3, NTH = 4;
+  static constexpr bool kNonlinear = true;
+  static constexpr bool kAdjoint = true;
+  static constexpr int kAngle = 1;
+
+  template <typename T>
+  static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {
+    const T sv = th[0], sw = th[1], r1 = th[2], r2 = th[3];
+    const T xi = x[0], ze = x[1], dxi = x[2], dze = x[3], om = x[4];
+    s.dt = dt;
+    mzero(s.F);
+    s.F[0][2] = T(1);
+    s.F[1][3] = T(1);
+    s.F[2][3] = -om;
+    s.F[2][4] = -dze;
+    s.F[3][2] = om;
+    s.F[3][4] = dxi;
+    s.c[0] = T(0);
+    s.c[1] = T(0);
+    s.c[2] = om * dze;
+    s.c[3] = -om * dxi;
+    s.c[4] = T(0);
+    const T sd = sqrt_(dt);
+    mzero(s.V);
+    s.V[2][0] = sd * sv;
+    s.V[3][1] = sd * sv;
+    s.V[4][2] = sd * sw;
+    const T rho2 = xi * xi + ze * ze;
+    T rho, rrho;
+    sqrt_rsqrt(rho2, rho, rrho);
+    const T irho2 = rrho * rrho;
+    mzero(s.H);
+    s.H[0][0] = xi * rrho;
+    s.H[0][1] = ze * rrho;
+    s.H[1][0] = -ze * irho2;
+    s.H[1][1] = xi * irho2;
+    s.r[0] = T(0);
+    s.r[1] = atan2_(ze, xi);
+    s.R[0][0] = r1;
+    s.R[0][1] = T(0);
+    s.R[1][0] = T(0);
+    s.R[1][1] = r2;
+    s.Rinv[0][0] = rcp(r1);
+    s.Rinv[0][1] = T(0);
+    s.Rinv[1][0] = T(0);
+    s.Rinv[1][1] = rcp(r2);
+  }
+
+  // theta-cotangent: C = dt diag(0, 0, sv^2, sv^2, sw^2), R = diag(r1, r2); A, b
+  // and the measurement terms do not depend on theta.
+  template <typename T>
+  static MS_DEV void vjp(const T* th, const T (&)[NX], T dt, const T (&)[NX][NX], const T (&)[NX],
+                         const T (&GC)[NX][NX], const T (&GR)[NY][NY], double (&out)[NTH]) {
+    const double h = dt;
+    out[0] += h * 2.0 * double(th[0]) * (double(GC[2][2]) + double(GC[3][3]));
+    out[1] += h * 2.0 * double(th[1]) * double(GC[4][4]);
+    out[2] += double(GR[0][0]);
+    out[3] += double(GR[1][1]);
+  }
 };
 
 }  // namespace ms
