@@ -52,12 +52,12 @@ def library_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_record(dtype):
-    """Per-launch counter figures of the scan kernels on this workload
+def counter_record(dtype, workload="cv4_T2p20"):
+    """Per-launch counter figures of the scan kernels on a workload
     (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device-copy calibration,
     SQ_INSTS_VALU_FLOPS_FP64 checked against a multiply of known size), and
     whether they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "counters_cv4_T2p20_%s.json" % dtype)
+    path = os.path.join(ROOT, "profiles", "counters_%s_%s.json" % (workload, dtype))
     if not os.path.exists(path):
         return None, False
     with open(path) as fh:
@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6144)
+    ap.add_argument("--cpu-sample-ct", type=int, default=16,
+                    help="tracks of the coordinated-turn CPU-baseline sample")
     ap.add_argument("--cpu-sample-tf", type=int, default=2 ** 20,
                     help="steps of the two-filter CPU-baseline sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
@@ -127,6 +129,8 @@ def main():
                     help="use the library's default schedule instead of autotuning it")
     ap.add_argument("--no-two-filter", action="store_true",
                     help="skip the two-filter smoother measurement")
+    ap.add_argument("--no-ct", action="store_true",
+                    help="skip the coordinated-turn (iterated nonlinear) measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -280,10 +284,16 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = nbytes
         res["flop_calibration_fp64"] = 1 << 24
+    ct_res = None
+    if not args.no_ct:
+        ct_res, wl_ct = measure_ct(args, ms, _lib, lib, timed, tdt, s)
+        res["coordinated_turn"] = ct_res
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
         if two_filter is not None:
             two_filter["cpu_baseline"] = cpu_baseline_two_filter(wl, args.cpu_sample_tf)
+        if ct_res is not None:
+            ct_res["cpu_baseline"] = cpu_baseline_ct(wl_ct, args.cpu_sample_ct)
     print(json.dumps(res))
 
 
@@ -309,6 +319,80 @@ def cpu_baseline(wl, n):
             "sample": "first %d steps of the same trajectory: sequential Kalman filter + RTS "
                       "smoother + log-likelihood + objective, gradients by autograd, FP64, "
                       "%.1f s" % (n, dt),
+            "cpu": cpu_info()}
+
+
+def measure_ct(args, ms, _lib, lib, timed, tdt, s):
+    """The paper's nonlinear experiment (Sec. 5.2): coordinated-turn tracks,
+    5 Gauss--Newton iterations from m0, each a full RTS-form solve; the last
+    one also gives P^s, the log-likelihood and the objective."""
+    import torch
+
+    import workloads
+
+    wl = workloads.ct()
+    p = ms.problem_from_workload(wl, dtype=tdt, device="cuda:0")
+    if not args.no_autotune:
+        # the autotuner times one linear solve: linearise about the simulated path
+        p.set_xbar(torch.as_tensor(wl.x_true))
+        ms.autotune(p)
+    f64 = torch.float64
+    out = dict(xbar=p._tiled(p.nx), S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx),
+               Ps=p._tiled(p.nsym), loglik=p._empty(p.n_seg, dtype=f64),
+               obj=p._empty(p.n_seg, dtype=f64))
+
+    def step():
+        ms.iterated_nonlinear(p, wl.n_iter, covariances=True, loglik=True, objective=True,
+                              out=out, natural=False)
+
+    ms_e, _, kern = timed(step, args.steps, args.warmup, True)
+    if args.no_graph:
+        ms_g = ms_e
+    else:
+        g = ms.GraphedSmooth(p, covariances=True, loglik=True, objective=True, grad=False,
+                             form="iterated", n_iter=wl.n_iter)
+        ms_g, _, _ = timed(g.replay, args.steps, args.warmup, False)
+    rec, fresh = counter_record(args.dtype, "ct5_64x2p14")
+    # per-launch averages pool the 5 iterations (the last with covariances)
+    roof = roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)
+    res = {"value": wl.n_steps / (ms_g * 1e-3), "unit": "time-steps/s",
+           "ms_per_step": ms_g, "eager_ms_per_step": round(ms_e, 4),
+           "workload": "coordinated-turn SDE (Sec. 5.2) nx=5 ny=2 (range, bearing), 64 tracks x "
+                       "2^14 steps dt=1e-3, 5 Gauss-Newton iterations from m0; x*, P^s, "
+                       "log-likelihood, objective of the last",
+           "n_iter": wl.n_iter, "n_steps": wl.n_steps,
+           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "roofline": roof}
+    return res, wl
+
+
+def first_tracks(wl, n):
+    """The first n segments of a workload of equal-length segments."""
+    import workloads
+
+    T = int(wl.seg_off[1] - wl.seg_off[0])
+    sub = workloads.Workload(**{**wl.__dict__})
+    sub.seg_off = wl.seg_off[:n + 1].copy()
+    sub.dt, sub.y = wl.dt[:n * T], wl.y[:, :n * T]
+    sub.theta, sub.m0, sub.P0 = wl.theta[:n], wl.m0[:n], wl.P0[:n]
+    sub.x_true = wl.x_true[:, :n * (T + 1)]
+    return sub
+
+
+def cpu_baseline_ct(wl, n_tracks):
+    """The plain-C sequential oracle (covariance Kalman filter + RTS per
+    iteration) running the same 5 iterations on the first n_tracks tracks,
+    one thread."""
+    from oracle import cref
+
+    sub = first_tracks(wl, n_tracks)
+    t0 = time.perf_counter()
+    cref.iterate(sub)
+    dt = time.perf_counter() - t0
+    n = int(sub.n_steps)
+    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the 64 tracks (%d steps), 5 iterations of the sequential C "
+                      "Kalman filter + RTS smoother, FP64, %.1f s" % (n_tracks, n, dt),
             "cpu": cpu_info()}
 
 

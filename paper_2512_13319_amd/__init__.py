@@ -345,20 +345,24 @@ def two_filter_smooth(p: Problem, covariances=True, loglik=True, out=None, natur
 
 
 def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, loglik=True,
-                       objective=True, grad=False, natural=True):
-    """xbar0: natural [nx, n_states] or None (m0 of each segment)."""
+                       objective=True, grad=False, out=None, natural=True):
+    """xbar0: natural [nx, n_states] or None (m0 of each segment).  `out` may
+    carry preallocated tiled buffers (keys xbar, S, v, xs, Ps, loglik, obj,
+    g_loglik, g_obj) to avoid allocations."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
-    xb = p._tiled(p.nx)
-    S = p._tiled(p.nsym)
-    v = p._tiled(p.nx)
-    xs = p._tiled(p.nx)
-    Ps = p._tiled(p.nsym) if covariances else None
-    ll = p._empty(p.n_seg, dtype=f64) if loglik else None
-    obj = p._empty(p.n_seg, dtype=f64) if objective else None
-    gl = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
-    gm = p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None
+    o = out or {}
+    get = lambda k, make: o[k] if o.get(k) is not None else make()
+    xb = get("xbar", lambda: p._tiled(p.nx))
+    S = get("S", lambda: p._tiled(p.nsym))
+    v = get("v", lambda: p._tiled(p.nx))
+    xs = get("xs", lambda: p._tiled(p.nx))
+    Ps = get("Ps", lambda: p._tiled(p.nsym)) if covariances else None
+    ll = get("loglik", lambda: p._empty(p.n_seg, dtype=f64)) if loglik else None
+    obj = get("obj", lambda: p._empty(p.n_seg, dtype=f64)) if objective else None
+    gl = get("g_loglik", lambda: p._empty(p.n_seg, p.n_theta, dtype=f64)) if grad else None
+    gm = get("g_obj", lambda: p._empty(p.n_seg, p.n_theta, dtype=f64)) if grad else None
     x0 = None if xbar0 is None else to_tiled(xbar0.to(p.device, p.dtype))
     _lib.check(lib.map_iterated_nonlinear(ctypes.byref(p.struct), int(n_iter), _ptr(x0), _ptr(xb),
                                           _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps), _ptr(ll),
@@ -385,37 +389,41 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True):
 
 
 class GraphedSmooth:
-    """A launch sequence of `smooth` (form "rts") or of `two_filter_smooth`
-    (form "two_filter") captured once into a HIP graph (torch.cuda.CUDAGraph
-    on ROCm) with fixed output buffers, then replayed.  Inputs are read from
-    the Problem's device buffers at replay time, so refreshing their contents
-    in place (same shapes) is seen by the next replay.  The sequence contains
-    kernel launches only (the accumulators are cleared by a kernel, not by
-    memset nodes)."""
+    """A launch sequence of `smooth` (form "rts"), of `two_filter_smooth`
+    (form "two_filter") or of `iterated_nonlinear` from m0 with `n_iter`
+    iterations (form "iterated") captured once into a HIP graph
+    (torch.cuda.CUDAGraph on ROCm) with fixed output buffers, then replayed.
+    Inputs are read from the Problem's device buffers at replay time, so
+    refreshing their contents in place (same shapes) is seen by the next
+    replay.  The sequence contains kernel launches only (the accumulators are
+    cleared by a kernel, not by memset nodes)."""
 
     def __init__(self, p: Problem, covariances=True, loglik=True, objective=True, grad=False,
-                 form="rts"):
-        if form not in ("rts", "two_filter"):
-            raise ValueError("form must be 'rts' or 'two_filter'")
+                 form="rts", n_iter=1):
+        if form not in ("rts", "two_filter", "iterated"):
+            raise ValueError("form must be 'rts', 'two_filter' or 'iterated'")
         if form == "two_filter" and (objective or grad):
             raise ValueError("the two-filter form has no objective or gradients")
         self.p = p
         f64 = torch.float64
         self.out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx),
+                        xbar=p._tiled(p.nx) if form == "iterated" else None,
                         Ps=p._tiled(p.nsym) if covariances else None,
                         loglik=p._empty(p.n_seg, dtype=f64) if loglik else None,
                         obj=p._empty(p.n_seg, dtype=f64) if objective else None,
                         g_loglik=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None,
                         g_obj=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None)
+        kw = dict(covariances=covariances, loglik=loglik)
         if form == "rts":
-            kw = dict(covariances=covariances, loglik=loglik, objective=objective, grad=grad)
-
             def run():
-                smooth(p, out=self.out, natural=False, **kw)
+                smooth(p, out=self.out, natural=False, objective=objective, grad=grad, **kw)
+        elif form == "two_filter":
+            def run():
+                two_filter_smooth(p, out=self.out, natural=False, **kw)
         else:
             def run():
-                two_filter_smooth(p, covariances=covariances, loglik=loglik, out=self.out,
-                                  natural=False)
+                iterated_nonlinear(p, n_iter, out=self.out, natural=False, objective=objective,
+                                   grad=grad, **kw)
         p.workspace()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
