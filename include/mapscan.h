@@ -126,7 +126,9 @@ typedef struct {
   const int64_t* seg_off_host;  /* optional host copy; when given it is validated */
   const void* dt;          /* device: one value (dt_stride 0) or tiled [1] per state, > 0 */
   int64_t dt_stride;       /* 0 (one shared value) or 1 (tiled per state) */
-  const void* y;           /* device, tiled [ny] per state: measurement of that state */
+  const void* y;           /* device, tiled [ny] per state: measurement of that state
+                            * (a segment's first state holds an unused value); never
+                            * NULL, also when n_steps = 0 */
   const void* m0;          /* device [n_seg][nx] prior means (m0_stride = nx, or 0: shared) */
   int64_t m0_stride;
   const void* P0;          /* device [n_seg][nx*nx] row-major SPD prior covariances */

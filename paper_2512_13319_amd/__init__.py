@@ -130,7 +130,9 @@ class Problem:
         self.n_steps = int(so[-1])
         self.n_states = self.n_steps + self.n_seg
         dt_np = np.asarray(dt.cpu().numpy() if torch.is_tensor(dt) else dt, dtype=np.float64).reshape(-1)
-        if dt_np.size == 1 or np.all(dt_np == dt_np[0]):
+        if dt_np.size == 0:
+            self.dt = t(np.ones(1))                       # no steps: any shared value
+        elif dt_np.size == 1 or np.all(dt_np == dt_np[0]):
             self.dt = t(dt_np[:1])                        # one shared step length
         else:
             self.dt = to_tiled(t(steps_to_states(so, self.n_states, dt_np[None])))

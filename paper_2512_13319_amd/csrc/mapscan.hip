@@ -150,7 +150,9 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
   }
   if (p.dt == nullptr) return fail(MAP_E_ARG, "dt is NULL");
   if (p.dt_stride != 0 && p.dt_stride != 1) return fail(MAP_E_ARG, "dt_stride must be 0 or 1");
-  if (p.n_steps > 0 && p.y == nullptr) return fail(MAP_E_ARG, "y is NULL");
+  // y is indexed by state (a segment's first state holds an unused value), so
+  // it is read even when there are no steps
+  if (p.y == nullptr) return fail(MAP_E_ARG, "y is NULL");
   if (p.m0 == nullptr || p.P0 == nullptr) return fail(MAP_E_ARG, "m0/P0 is NULL");
   if (p.m0_stride < 0 || p.P0_stride < 0 || p.theta_stride < 0)
     return fail(MAP_E_ARG, "negative stride");

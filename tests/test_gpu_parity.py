@@ -68,6 +68,10 @@ CASES = {
     # merged final tile that contains three segment heads (states 2035, 2040,
     # 2042 of 2055), one of them a one-step segment
     "batched_tail_heads": lambda: workloads.cv_batched(lens=[1500, 533, 4, 1, 12], seed=18),
+    # segments without steps (a lone prior state): first, last, and runs of
+    # them inside a tile
+    "batched_empty_segments": lambda: workloads.cv_batched(lens=[0, 1500, 0, 0, 533, 0, 1, 0],
+                                                           seed=19),
 }
 
 
@@ -240,3 +244,22 @@ def test_autotune_records_and_reuses_schedule(tmp_path):
     torch.cuda.synchronize()
     assert rel_err(planes_T(r["xs"]), o["xs"]) <= 1e-9
     assert rel_err(sym_full(ms, r["Ps"], wl.nx), o["Ps"]) <= 1e-9
+
+
+def test_problem_without_steps():
+    """n_steps = 0: every segment is its prior; filter, RTS and two-filter
+    forms return m0, P0, zero log-likelihood and objective."""
+    ms = _mapscan()
+    wl = workloads.cv_batched(lens=[0, 0, 0, 0, 0], seed=20)
+    assert wl.n_steps == 0
+    p = ms.problem_from_workload(wl, dtype=torch.float64)
+    r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
+    t = ms.two_filter_smooth(p, covariances=True, loglik=True)
+    torch.cuda.synchronize()
+    for out in (r, t):
+        assert np.abs(planes_T(out["xs"]) - wl.m0).max() < 1e-14
+        assert np.abs(sym_full(ms, out["Ps"], 4) - wl.P0).max() < 1e-15
+        assert not out["loglik"].cpu().numpy().any()
+    # the prior term 1/2 |x - m0|^2_{P0^-1} at x = S^-1 v = m0 up to rounding
+    assert np.abs(r["obj"].cpu().numpy()).max() < 1e-24
+    assert not r["g_loglik"].cpu().numpy().any() and not r["g_obj"].cpu().numpy().any()

@@ -489,3 +489,24 @@ def test_ct_iterates_c_and_torch_agree_and_decrease():
         obj = [ref.map_objective_nonlinear("ct", seg["theta"], x, seg["dt"], seg["y"], seg["m0"],
                                            seg["P0"], 5).item() for x in its]
         assert all(b <= a + 1e-9 * abs(a) for a, b in zip(obj[1:], obj[2:]))
+
+
+def test_zero_step_segments():
+    """A segment without steps is its prior alone: x* = m0, P^s = P0, zero
+    log-likelihood and objective; its neighbours are unaffected (dense
+    conditioning per segment), in the RTS and the two-filter forms."""
+    wl = workloads.cv_batched(lens=[0, 5, 0, 0, 30, 0], d=2, dt=0.05, seed=41)
+    o = cref.smooth(wl)
+    t = cref.two_filter(wl)
+    for s in range(wl.n_seg):
+        st = wl.seg_states(s)
+        if wl.seg_off[s + 1] == wl.seg_off[s]:
+            for out in (o, t):
+                assert np.array_equal(out["xs"][st][0], wl.m0[s])
+                assert np.abs(out["Ps"][st][0] - wl.P0[s]).max() < 1e-15
+            assert o["loglik"][s] == 0.0 and o["mstar"][s] == 0.0
+            continue
+        mean, cov, ll = _dense.dense_posterior(wl, s)
+        for out in (o, t):
+            assert np.abs(out["xs"][st] - mean).max() <= 1e-11 * np.abs(mean).max()
+        assert abs(o["loglik"][s] - ll) <= 1e-10 * abs(ll)
