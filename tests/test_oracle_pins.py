@@ -510,3 +510,61 @@ def test_zero_step_segments():
         for out in (o, t):
             assert np.abs(out["xs"][st] - mean).max() <= 1e-11 * np.abs(mean).max()
         assert abs(o["loglik"][s] - ll) <= 1e-10 * abs(ll)
+
+
+# ------------------------------------------------------------------ sub-stepped block elements
+def _euler_block(F, c, Q, H, Rinv, ys, r, h, sign_qj=+1.0):
+    """The element ODE of Sec. 4.2 (eq. backwardLQT) integrated by explicit
+    Euler over a block of len(ys) substeps of length h, written in original
+    time (d/dt = -d/ds, F~ = -F, c~ = -c), from the boundary value
+    (I, 0, 0, 0, 0); substep j uses the measurement at its end.  sign_qj = +1
+    is the corrected A equation (+A Q J), -1 the printed one (-A Q J^T)."""
+    n = F.shape[0]
+    A, b, C, eta, J = np.eye(n), np.zeros(n), np.zeros((n, n)), np.zeros(n), np.zeros((n, n))
+    for y in ys:
+        dA = -A @ (sign_qj * Q @ J + F)
+        db = A @ (Q @ eta - c)
+        dC = A @ Q @ A.T
+        deta = -F.T @ eta - J @ Q @ eta + J @ c + H.T @ Rinv @ (y - r)
+        dJ = -F.T @ J - J @ F - J @ Q @ J + H.T @ Rinv @ H
+        A, b, C, eta, J = A + h * dA, b + h * db, C + h * dC, eta + h * deta, J + h * dJ
+    return A, b, C, eta, J
+
+
+def test_substep_euler_block_converges_to_the_exact_block_with_corrected_sign():
+    """Sub-stepped blocks (the paper's T blocks x n Euler substeps): over a
+    block of fixed length, the Euler-integrated element ODE approaches the
+    exact combination of the n one-step elements (the oracle's run over the
+    block's steps, Sec. 4.1 rule) at first order in the substep with the
+    A equation read as +A Q J, and stays O(1) away with the printed sign."""
+    rng = np.random.default_rng(5)
+    nx, ny = 3, 2
+    F = rng.normal(0, 0.6, (nx, nx))
+    c = rng.normal(0, 0.5, nx)
+    L = rng.normal(0, 1.0, (nx, nx))
+    Q = L @ L.T
+    H = rng.normal(0, 1.0, (ny, nx))
+    R = np.diag([0.3, 0.5])
+    r = rng.normal(0, 0.2, ny)
+    Tb = 0.8
+    errs, errs_printed = [], []
+    for n in (20, 40, 80, 160):
+        h = Tb / n
+        ts = h * np.arange(1, n + 1)
+        ys = np.stack([np.sin(1.3 * ts + 0.2), np.cos(0.7 * ts)], 1)
+        # the oracle's run of these n steps: the run after state 0 of an
+        # n-step segment (a linear model with these constant terms)
+        wl = workloads.linear_random(T=n, nx=nx, ny=ny, nw=nx, dt=h, time_varying=False, seed=1)
+        wl.lin = dict(F=F, c=c, L=L, W=np.eye(nx), H=H, r=r, R=R)
+        wl.lin = {k: (np.broadcast_to(v, (n,) + v.shape).copy() if k in ("F", "c", "H", "r") else v)
+                  for k, v in wl.lin.items()}
+        wl.y = ys.T.copy()
+        o = cref.two_filter(wl, suffix=True)
+        exact = [o["suf"][k][0] for k in ("A", "b", "C", "eta", "J")]
+        for sign, out in ((+1.0, errs), (-1.0, errs_printed)):
+            eu = _euler_block(F, c, Q, H, np.linalg.inv(R), ys, r, h, sign)
+            out.append(max(np.abs(e - x).max() / max(1.0, np.abs(x).max()) for e, x in zip(eu, exact)))
+    ratios = [a / b for a, b in zip(errs[:-1], errs[1:])]
+    assert all(1.8 < q < 2.2 for q in ratios), (errs, ratios)
+    assert errs[-1] < 2e-2
+    assert min(errs_printed) > 20 * errs[-1], (errs_printed, errs)
