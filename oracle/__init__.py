@@ -15,11 +15,14 @@ the seeded inputs of `workloads/`.
              conditional value function of the later steps by the paper's
              combination rule, joined with the forward filter.
   models.py  the models' drift/measurement Taylor terms.
+  lti.py     exact (Van Loan, scipy expm) discretisation of time-invariant
+             linear models, re-expressed as terms of the implicit-Euler step.
 
 Every function is pinned by tests under `tests/test_oracle_*.py` against
 things that do not come from itself: dense Gaussian conditioning, dense least
 squares, the discrete and continuous algebraic Riccati equations, central
 finite differences of a dense likelihood, and nonlinear least squares; the
 two-filter smoother also against the dense likelihood of the later
-measurements given one state (its backward filter).
+measurements given one state (its backward filter); the exact discretisation
+against closed forms and dense conditioning with exact transitions.
 """

@@ -568,3 +568,120 @@ def test_substep_euler_block_converges_to_the_exact_block_with_corrected_sign():
     assert all(1.8 < q < 2.2 for q in ratios), (errs, ratios)
     assert errs[-1] < 2e-2
     assert min(errs_printed) > 20 * errs[-1], (errs_printed, errs)
+
+
+# ------------------------------------------------------------------ exact LTI discretisation
+from oracle import lti as _lti
+
+
+def test_van_loan_matches_constant_velocity_closed_forms():
+    """Wiener velocity: Phi = [[1, dt], [0, 1]], Qd = q [[dt^3/3, dt^2/2], [dt^2/2, dt]];
+    damped velocity (Ornstein-Uhlenbeck) with its integral: the classical formulas."""
+    q, dt = 0.7, 0.05
+    F = np.array([[0.0, 1.0], [0.0, 0.0]])
+    L = np.array([[0.0], [1.0]])
+    Phi, u, Qd = _lti.van_loan(F, np.zeros(2), L, q * np.eye(1), dt)
+    assert np.abs(Phi - [[1, dt], [0, 1]]).max() < 1e-15
+    assert np.abs(Qd - q * np.array([[dt ** 3 / 3, dt ** 2 / 2], [dt ** 2 / 2, dt]])).max() < 1e-16
+    g = 0.8
+    F = np.array([[0.0, 1.0], [0.0, -g]])
+    Phi, u, Qd = _lti.van_loan(F, np.array([0.3, -0.2]), L, q * np.eye(1), dt)
+    e = np.exp(-g * dt)
+    assert np.abs(Phi - [[1, (1 - e) / g], [0, e]]).max() < 1e-15
+    qvv = q * (1 - e * e) / (2 * g)
+    qpv = q * (1 - e) ** 2 / (2 * g * g)
+    qpp = q / g ** 2 * (dt - 2 * (1 - e) / g + (1 - e * e) / (2 * g))
+    assert np.abs(Qd - [[qpp, qpv], [qpv, qvv]]).max() < 1e-15
+    # u = int_0^dt e^{F s} ds c
+    s = np.linspace(0, dt, 20001)
+    integrand = np.stack([np.array([[1, (1 - np.exp(-g * t)) / g], [0, np.exp(-g * t)]]) @ [0.3, -0.2]
+                          for t in s])
+    assert np.abs(u - np.trapezoid(integrand, s, axis=0)).max() < 1e-11
+
+
+def _exact_joint(wl, Fc, cc, Lc, Wc, H, r, R):
+    """Dense joint Gaussian of (x_0..x_T) and y under the exact transitions."""
+    T = wl.n_steps
+    nx, ny = wl.nx, wl.ny
+    dt = wl.dt[0]
+    Phi, u, Qd = _lti.van_loan(Fc, cc, Lc, Wc, dt)
+    n = (T + 1) * nx
+    mu = np.zeros(n)
+    mu[:nx] = wl.m0[0]
+    G = np.zeros((n, n))
+    G[:nx, :nx] = np.eye(nx)
+    Cxi = np.zeros((n, n))
+    Cxi[:nx, :nx] = wl.P0[0]
+    for k in range(T):
+        mu[(k + 1) * nx:(k + 2) * nx] = Phi @ mu[k * nx:(k + 1) * nx] + u
+        G[(k + 1) * nx:(k + 2) * nx] = Phi @ G[k * nx:(k + 1) * nx]
+        G[(k + 1) * nx:(k + 2) * nx, (k + 1) * nx:(k + 2) * nx] += np.eye(nx)
+        Cxi[(k + 1) * nx:(k + 2) * nx, (k + 1) * nx:(k + 2) * nx] = Qd
+    Sx = G @ Cxi @ G.T
+    Hb = np.zeros((T * ny, n))
+    Rb = np.zeros((T * ny, T * ny))
+    for k in range(T):
+        Hb[k * ny:(k + 1) * ny, (k + 1) * nx:(k + 2) * nx] = H
+        Rb[k * ny:(k + 1) * ny, k * ny:(k + 1) * ny] = R / dt
+    yv = wl.y.T.reshape(-1)
+    my = Hb @ mu + np.tile(r, T)
+    Sy = Hb @ Sx @ Hb.T + Rb
+    K = np.linalg.solve(Sy, Hb @ Sx).T
+    mean = mu + K @ (yv - my)
+    cov = Sx - K @ Hb @ Sx
+    return mean.reshape(T + 1, nx), cov
+
+
+def lti_exact_workload(T=30, dt=0.08, seed=51, gamma=0.6):
+    """A damped 2-D constant-velocity track with a drift offset, as a general
+    linear workload whose terms are the exact discretisation's (oracle side)."""
+    wl = workloads.cv(T=T, d=2, dt=dt, gamma=gamma, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                      P0=1e-2 * np.eye(4), seed=seed)
+    F = np.zeros((4, 4)); F[:2, 2:] = np.eye(2); F[2:, 2:] = -gamma * np.eye(2)
+    c = np.array([0.0, 0.0, 0.15, -0.1])
+    L = np.vstack([np.zeros((2, 2)), np.eye(2)])
+    W = 0.5 * np.eye(2)
+    H = np.hstack([np.eye(2), np.zeros((2, 2))])
+    r = np.array([0.02, -0.03])
+    R = 0.05 * np.eye(2)
+    Ft, ct, Lt, Wt = _lti.implicit_equivalent(F, c, L, W, dt)
+    # per-step arrays for F, c, H, r (the workloads' linear-model layout)
+    per = lambda m: np.broadcast_to(m, (T,) + m.shape).copy()
+    lin = dict(F=per(Ft), c=per(ct), L=Lt, W=Wt, H=per(H), r=per(r), R=R)
+    w = workloads.Workload(name="lti_exact", model="linear", nx=4, ny=2, nw=4,
+                           seg_off=wl.seg_off, dt=wl.dt, y=wl.y, theta=np.zeros((1, 0)),
+                           m0=wl.m0, P0=wl.P0, x_true=wl.x_true, lin=lin)
+    return w, (F, c, L, W, H, r, R)
+
+
+def test_exact_discretisation_equals_dense_conditioning():
+    """The oracle's filter and smoother on the implicit-equivalent terms give
+    the posterior of the exactly discretised model (dense conditioning with
+    Phi = e^{F dt}, Qd from scipy's expm written out here)."""
+    wl, (F, c, L, W, H, r, R) = lti_exact_workload()
+    o = cref.smooth(wl)
+    mean, cov = _exact_joint(wl, F, c, L, W, H, r, R)
+    nx = 4
+    assert np.abs(o["xs"] - mean).max() <= 1e-11 * np.abs(mean).max()
+    dcov = np.stack([cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] for k in range(wl.n_steps + 1)])
+    assert np.abs(o["Ps"] - dcov).max() <= 1e-11 * np.abs(dcov).max()
+
+
+def test_implicit_euler_and_exact_agree_to_first_order():
+    """Both discretisations approximate the same continuous-time problem: with
+    one smooth measurement signal sampled on each grid, the smoothed means on a
+    fixed horizon differ by O(dt)."""
+    diffs = []
+    for T in (40, 80, 160, 320):
+        wl, (F, c, L, W, H, r, R) = lti_exact_workload(T=T, dt=3.2 / T, seed=52)
+        t = wl.dt[0] * np.arange(1, T + 1)
+        wl.y = np.stack([5 + 0.4 * np.sin(1.1 * t), 5 + 0.3 * np.cos(0.8 * t) + 0.2 * t])
+        ex = cref.smooth(wl)["xs"]
+        w2 = workloads.Workload(**{**wl.__dict__})
+        per = lambda m: np.broadcast_to(m, (T,) + m.shape).copy()
+        w2.lin = dict(F=per(F), c=per(c), L=L, W=W, H=per(H), r=per(r), R=R)
+        w2.nw = 2
+        ie = cref.smooth(w2)["xs"]
+        diffs.append(np.abs(ex - ie).max())
+    q = [a / b for a, b in zip(diffs[:-1], diffs[1:])]
+    assert all(1.7 < x < 2.3 for x in q), (diffs, q)
