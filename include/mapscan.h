@@ -247,6 +247,25 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
 map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,
                         int32_t* chunk_out, void* stream);
 
+/* Exact element dynamics for a time-invariant linear-affine model (element
+ * variant; only the element build changes).  For dx/dt = F x + c + L w
+ * (w white with spectral density W) the exact transition over a step dt,
+ * x_k = e^{F dt} x_{k-1} + u + N(0, Qd) (Van Loan), read backwards as
+ * x_{k-1} = A x_k + b + N(0, C) with A = e^{-F dt}, b = -A u, C = A Qd A^T, is
+ * returned as the terms of the library's one-step element (Sec. 4.2, one
+ * explicit-Euler step of eq. backwardLQT: A = I - dt F~, b = -dt c~,
+ * C = dt L~ W~ L~^T):
+ *   F_out [nx*nx] = (I - A) / dt,  c_out [nx] = -b / dt,  L_out [nx*nx] with
+ *   L_out L_out^T = C / dt and W~ = I.
+ * A MAP_MODEL_LINEAR problem with F = F_out, c = c_out, L = L_out, W = I (nw = nx)
+ * and the model's H, r, R then solves the exactly discretised dynamics (the
+ * measurement term stays dt H^T R^{-1} H at the step's end).  Host arrays,
+ * row-major doubles; c may be NULL (no offset).  Host-only; launches nothing.
+ * Errors: dimensions outside [1, 8], dt <= 0, NULL or non-finite inputs. */
+map_status map_lti_exact_terms(int32_t nx, int32_t nw, const double* F, const double* c,
+                               const double* L, const double* W, double dt, double* F_out,
+                               double* c_out, double* L_out);
+
 /* The schedule (states per lane: 4, 8 or 16) the scan entry points use for
  * this problem: p->chunk if set, else the choice map_autotune recorded for
  * its shape, else the library's heuristic.  Host-only; launches nothing. */

@@ -5,8 +5,7 @@ For dx/dt = F x + c + L w (w white, spectral density W) the transition over
 dt is x_k = Phi x_{k-1} + u + w_k with Phi = e^{F dt},
 u = int_0^dt e^{F s} ds c and w_k ~ N(0, Qd), Qd = int_0^dt e^{F s} Q e^{F^T s} ds,
 Q = L W L^T (Van Loan: the exponential of [[-F, Q], [0, F^T]] dt has
-e^{F^T dt} in its lower-right block and Phi^{-1} Qd... in its upper-right,
-Qd = e^{F dt} times that block).  Written backwards, x_{k-1} = A x_k + b + noise
+e^{F^T dt} in its lower-right block and e^{-F dt} Qd in its upper-right one).  Written backwards, x_{k-1} = A x_k + b + noise
 with A = e^{-F dt}, b = -A u and covariance C = A Qd A^T: these are the exact
 dynamics parts of the one-step element (Sec. 4.2 integrates eq. backwardLQT
 with the measurement term exactly over the step when H = 0).

@@ -26,7 +26,7 @@ from . import _lib
 from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
-           "two_filter_smooth", "autotune", "schedule",
+           "two_filter_smooth", "autotune", "schedule", "lti_exact_terms",
            "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
            "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
@@ -255,6 +255,26 @@ def autotune(p: Problem, cache_path=None) -> int:
     _lib.check(lib.map_autotune(ctypes.byref(p.struct), _ptr(ws), ws.numel(), path,
                                 ctypes.byref(out), _stream()))
     return int(out.value)
+
+
+def lti_exact_terms(F, c, L, W, dt):
+    """Terms (F~, c~, L~, W~ = I) of the library's one-step element that make it
+    the exact discretisation of the time-invariant model dx/dt = F x + c + L w
+    over a step dt (see map_lti_exact_terms).  Host numpy arrays in and out;
+    use them as F, c, L, W of a "linear" Problem (nw = nx)."""
+    lib = _lib.load()
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    nx, nw = F.shape[0], L.shape[1]
+    c = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+    Ft = np.empty((nx, nx))
+    ct = np.empty(nx)
+    Lt = np.empty((nx, nx))
+    p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    _lib.check(lib.map_lti_exact_terms(nx, nw, p(F), p(c), p(L), p(W), float(dt), p(Ft), p(ct),
+                                       p(Lt)))
+    return Ft, ct, Lt, np.eye(nx)
 
 
 def schedule(p: Problem) -> int:

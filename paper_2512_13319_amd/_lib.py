@@ -16,7 +16,7 @@ STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: 
 EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "map_filter_scan",
            "map_smoother_scan", "map_smooth", "map_two_filter_smooth", "map_iterated_nonlinear",
            "map_backward",
-           "map_autotune", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
+           "map_autotune", "map_lti_exact_terms", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
            "map_last_error", "map_abi_version"]
 PROF_KINDS = {"filter_up": 0, "filter_down": 1, "fused_down": 2, "traj_up": 3, "traj_down": 4,
               "traj_down_adjoint": 5, "aux": 6, "two_filter_up": 7, "two_filter_down": 8}
@@ -76,6 +76,7 @@ def load(path: str | None = None):
     lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, sz, vp]
     lib.map_autotune.argtypes = [P, vp, sz, ctypes.c_char_p, ctypes.POINTER(i32), vp]
     lib.map_schedule.argtypes = [P, ctypes.POINTER(i32)]
+    lib.map_lti_exact_terms.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]
     lib.map_profile_enable.argtypes = [i32]
     lib.map_profile_reset.argtypes = []
     lib.map_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <map>
 #include <mutex>
@@ -12,6 +13,7 @@
 
 #include "models.h"
 #include "runner.h"
+#include "lti.h"
 
 namespace ms {
 
@@ -512,6 +514,44 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
     }
   }
   *chunk_out = best;
+  return MAP_OK;
+}
+
+// Finite tests on the stored bit pattern: the library is built with
+// -ffinite-math-only, under which the compiler may fold std::isfinite (or any
+// test of a double value) to true.  The bytes are read as integers.
+static bool finite_at(const double* p) {
+  uint64_t u;
+  memcpy(&u, p, sizeof(u));
+  return ((u >> 52) & 0x7ff) != 0x7ff;
+}
+static bool finite_value(double x) {
+  volatile double v = x;
+  const volatile unsigned char* b = reinterpret_cast<const volatile unsigned char*>(&v);
+  uint64_t u = 0;
+  for (int i = 0; i < 8; ++i) u |= uint64_t(b[i]) << (8 * i);
+  return ((u >> 52) & 0x7ff) != 0x7ff;
+}
+
+map_status map_lti_exact_terms(int32_t nx, int32_t nw, const double* F, const double* c,
+                               const double* L, const double* W, double dt, double* F_out,
+                               double* c_out, double* L_out) {
+  if (nx < 1 || nx > 8 || nw < 1 || nw > 8)
+    return fail(MAP_E_DIM, "dimensions (nx, nw) = (%d, %d) outside [1, 8]", nx, nw);
+  if (!finite_value(dt) || !(dt > 0.0)) return fail(MAP_E_ARG, "dt must be finite and > 0");
+  if (F == nullptr || L == nullptr || W == nullptr || F_out == nullptr || c_out == nullptr ||
+      L_out == nullptr)
+    return fail(MAP_E_ARG, "F/L/W or an output is NULL");
+  for (int i = 0; i < nx * nx; ++i)
+    if (!finite_at(F + i)) return fail(MAP_E_NUMERIC, "F is not finite");
+  for (int i = 0; i < nx * nw; ++i)
+    if (!finite_at(L + i)) return fail(MAP_E_NUMERIC, "L is not finite");
+  for (int i = 0; i < nw * nw; ++i)
+    if (!finite_at(W + i)) return fail(MAP_E_NUMERIC, "W is not finite");
+  if (c != nullptr)
+    for (int i = 0; i < nx; ++i)
+      if (!finite_at(c + i)) return fail(MAP_E_NUMERIC, "c is not finite");
+  lti::exact_terms(nx, nw, F, c, L, W, dt, F_out, c_out, L_out);
   return MAP_OK;
 }
 

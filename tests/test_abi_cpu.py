@@ -226,3 +226,34 @@ def test_schedule_query():
     assert lib.map_schedule(ctypes.byref(p), None) == -1
     p.chunk = 3
     assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == -1
+
+
+def test_lti_exact_terms_against_the_oracle():
+    """The library's host-side exact discretisation (Taylor scaling and
+    squaring, Jacobi) against the oracle's (scipy expm, eigh): same F~, c~ and
+    L~ L~^T; argument errors are reported."""
+    import paper_2512_13319_amd as ms
+    from oracle import lti
+    rng = np.random.default_rng(9)
+    cases = [(np.array([[0.0, 1.0], [0.0, 0.0]]), np.zeros(2), np.array([[0.0], [1.0]]), 0.7 * np.eye(1), 1e-3),
+             (np.array([[0.0, 1.0], [-0.5, -0.2]]), np.array([0.3, -0.1]), rng.normal(size=(2, 2)),
+              np.eye(2), 0.05)]
+    F4 = np.zeros((4, 4)); F4[:2, 2:] = np.eye(2); F4[2:, 2:] = -0.6 * np.eye(2)
+    cases.append((F4, np.array([0, 0, 0.15, -0.1]), np.vstack([np.zeros((2, 2)), np.eye(2)]),
+                  0.5 * np.eye(2), 0.08))
+    for F, c, L, W, dt in cases:
+        a = ms.lti_exact_terms(F, c, L, W, dt)
+        b = lti.implicit_equivalent(F, c, L, W, dt)
+        assert np.abs(a[0] - b[0]).max() <= 1e-11 * max(1.0, np.abs(b[0]).max())
+        assert np.abs(a[1] - b[1]).max() <= 1e-11 * max(1.0, np.abs(b[1]).max())
+        Ca, Cb = a[2] @ a[2].T, b[2] @ b[2].T
+        assert np.abs(Ca - Cb).max() <= 1e-12 * np.abs(Cb).max()
+    lib = _lib.load()
+    F = np.eye(2)
+    L = np.eye(2)
+    out = np.empty(4)
+    p = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    assert lib.map_lti_exact_terms(2, 2, p(F), None, p(L), p(L), 0.0, p(out), p(out), p(out)) == -1
+    assert lib.map_lti_exact_terms(9, 2, p(F), None, p(L), p(L), 0.1, p(out), p(out), p(out)) == -2
+    Fn = F.copy(); Fn[0, 0] = np.nan
+    assert lib.map_lti_exact_terms(2, 2, p(Fn), None, p(L), p(L), 0.1, p(out), p(out), p(out)) == -5
