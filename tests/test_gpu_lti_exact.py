@@ -13,6 +13,19 @@ from tests.test_gpu_parity import TOL, TORCH_DT, planes_T, rel_err, sym_full
 pytestmark = pytest.mark.gpu
 
 
+def rel_err_floor(gpu, refv):
+    """rel_err with each component's scale floored at 1e-6 of the largest
+    one: the square root of C / dt is not unique, and where the oracle's
+    (LAPACK eigh) mixes the two identical axes, structurally zero cross-axis
+    covariances come out as rounding noise (~1e-20 of the largest entry) on its
+    side and as exact zeros on the library's side (its Jacobi rotations skip
+    zero entries).  Only such components reach the floor."""
+    g = np.asarray(gpu, dtype=np.float64).reshape(gpu.shape[0], -1)
+    r = np.asarray(refv, dtype=np.float64).reshape(refv.shape[0], -1)
+    den = np.maximum(np.abs(r).max(0), 1e-6 * np.abs(r).max())
+    return float((np.abs(g - r).max(0) / den).max())
+
+
 def _cv_terms(gamma, q, r, c):
     F = np.zeros((4, 4)); F[:2, 2:] = np.eye(2); F[2:, 2:] = -gamma * np.eye(2)
     L = np.vstack([np.zeros((2, 2)), np.eye(2)])
@@ -54,7 +67,7 @@ def test_lti_exact_parity(T, gamma, dtype):
     r = ms.smooth(p, covariances=True, loglik=True, objective=True)
     torch.cuda.synchronize()
     e_xs = rel_err(planes_T(r["xs"]), o["xs"])
-    e_Ps = rel_err(sym_full(ms, r["Ps"], 4), o["Ps"])
+    e_Ps = rel_err_floor(sym_full(ms, r["Ps"], 4), o["Ps"])
     e_ll = abs(r["loglik"].item() - o["loglik"][0]) / abs(o["loglik"][0])
     e_ob = abs(r["obj"].item() - o["mstar"][0]) / abs(o["mstar"][0])
     msg = f"lti exact T={T} gamma={gamma} {dtype}: xs {e_xs:.2e} Ps {e_Ps:.2e} ll {e_ll:.2e} obj {e_ob:.2e}"
@@ -72,7 +85,7 @@ def test_lti_exact_full_wiener_velocity():
     r = ms.smooth(p, covariances=True, loglik=True, objective=False)
     torch.cuda.synchronize()
     e_xs = rel_err(planes_T(r["xs"]), o["xs"])
-    e_Ps = rel_err(sym_full(ms, r["Ps"], 4), o["Ps"])
+    e_Ps = rel_err_floor(sym_full(ms, r["Ps"], 4), o["Ps"])
     e_ll = abs(r["loglik"].item() - o["loglik"][0]) / abs(o["loglik"][0])
     print(f"lti exact full: xs {e_xs:.2e} Ps {e_Ps:.2e} ll {e_ll:.2e}")
     assert max(e_xs, e_Ps, e_ll) <= 1e-9
