@@ -129,6 +129,8 @@ def main():
                     help="use the library's default schedule instead of autotuning it")
     ap.add_argument("--no-two-filter", action="store_true",
                     help="skip the two-filter smoother measurement")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the exact-discretisation (linear-model path) measurement")
     ap.add_argument("--no-ct", action="store_true",
                     help="skip the coordinated-turn (iterated nonlinear) measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -284,6 +286,10 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = nbytes
         res["flop_calibration_fp64"] = 1 << 24
+    ex_res = None
+    if not args.no_exact:
+        ex_res, wl_ex = measure_exact(args, ms, _lib, lib, timed, tdt, s, wl)
+        res["exact_dynamics"] = ex_res
     ct_res = None
     if not args.no_ct:
         ct_res, wl_ct = measure_ct(args, ms, _lib, lib, timed, tdt, s)
@@ -294,6 +300,8 @@ def main():
             two_filter["cpu_baseline"] = cpu_baseline_two_filter(wl, args.cpu_sample_tf)
         if ct_res is not None:
             ct_res["cpu_baseline"] = cpu_baseline_ct(wl_ct, args.cpu_sample_ct)
+        if ex_res is not None:
+            ex_res["cpu_baseline"] = cpu_baseline_exact(wl_ex, args.cpu_sample_tf)
     print(json.dumps(res))
 
 
@@ -364,6 +372,78 @@ def measure_ct(args, ms, _lib, lib, timed, tdt, s):
            "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
            "roofline": roof}
     return res, wl
+
+
+def exact_terms_cv(q, gamma=0.0):
+    import numpy as np
+    F = np.zeros((4, 4)); F[:2, 2:] = np.eye(2); F[2:, 2:] = -gamma * np.eye(2)
+    L = np.vstack([np.zeros((2, 2)), np.eye(2)])
+    return F, np.zeros(4), L, q * np.eye(2)
+
+
+def measure_exact(args, ms, _lib, lib, timed, tdt, s, wl):
+    """The same 2^20-step track with exact (Van Loan) dynamics in the elements
+    (map_lti_exact_terms), run through the general linear model: filter,
+    smoother with covariances, log-likelihood and objective."""
+    import numpy as np
+    import torch
+
+    import workloads
+
+    q, r, dt = 0.5, 0.05, float(wl.dt[0])
+    Ft, ct, Lt, Wt = ms.lti_exact_terms(*exact_terms_cv(q), dt)
+    lin = dict(F=Ft, c=ct, L=Lt, W=Wt, H=np.hstack([np.eye(2), np.zeros((2, 2))]),
+               r=np.zeros(2), R=r * np.eye(2))
+    wx = workloads.Workload(name="cv_exact", model="linear", nx=4, ny=2, nw=4, seg_off=wl.seg_off,
+                            dt=wl.dt, y=wl.y, theta=np.zeros((1, 0)), m0=wl.m0, P0=wl.P0,
+                            x_true=wl.x_true, lin=lin)
+    p = ms.problem_from_workload(wx, dtype=tdt, device="cuda:0")
+    if not args.no_autotune:
+        ms.autotune(p)
+    f64 = torch.float64
+    out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx), Ps=p._tiled(p.nsym),
+               loglik=p._empty(1, dtype=f64), obj=p._empty(1, dtype=f64))
+
+    def step():
+        ms.smooth(p, covariances=True, loglik=True, objective=True, out=out, natural=False)
+
+    ms_e, _, kern = timed(step, args.steps, args.warmup, True)
+    if args.no_graph:
+        ms_g = ms_e
+    else:
+        g = ms.GraphedSmooth(p, covariances=True, loglik=True, objective=True, grad=False)
+        ms_g, _, _ = timed(g.replay, args.steps, args.warmup, False)
+    rec, fresh = counter_record(args.dtype, "lin4exact_T2p20")
+    res = {"value": wx.n_steps / (ms_g * 1e-3), "unit": "time-steps/s", "ms_per_step": ms_g,
+           "eager_ms_per_step": round(ms_e, 4),
+           "workload": "the same 2-D constant-velocity track (T=2^20, dt=1e-3) with exact "
+                       "(matrix-exponential) dynamics in the elements, general linear model "
+                       "nx=4 ny=2 nw=4; x*, P^s, log-likelihood, objective",
+           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)}
+    return res, wx
+
+
+def cpu_baseline_exact(wx, n):
+    """The plain-C sequential oracle (covariance Kalman filter + RTS smoother +
+    likelihood + objective) on the oracle's own exact terms, first n steps."""
+    import numpy as np
+
+    from oracle import cref, lti
+
+    q, r, dt = 0.5, 0.05, float(wx.dt[0])
+    Ft, ct, Lt, Wt = lti.implicit_equivalent(*exact_terms_cv(q), dt)
+    sub = workloads_prefix(wx, n)
+    per = lambda m: np.broadcast_to(m, (n,) + m.shape)
+    sub.lin = dict(F=per(Ft), c=per(ct), L=Lt, W=Wt, H=per(wx.lin["H"]), r=per(wx.lin["r"]),
+                   R=wx.lin["R"])
+    t0 = time.perf_counter()
+    cref.smooth(sub)
+    dt_ = time.perf_counter() - t0
+    return {"value": n / dt_, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the same track: sequential C Kalman filter + RTS "
+                      "smoother + log-likelihood + objective on exact terms, FP64, %.1f s"
+                      % (n, dt_), "cpu": cpu_info()}
 
 
 def first_tracks(wl, n):
