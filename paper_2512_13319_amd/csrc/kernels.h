@@ -309,6 +309,47 @@ MS_DEVONLY void shfl_elem(Elem<T, N>& o, const Elem<T, N>& e, int src) {
   shfl_vec(o.eta, e.eta, src);
   shfl_sym(o.J, e.J, src);
 }
+// element <-> ElemSz contiguous values (LDS staging)
+template <typename T, int N>
+MS_DEVONLY void pack_elem(T* w, const Elem<T, N>& e) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) w[c++] = e.A[r][q];
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[c++] = e.b[r];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) w[c++] = e.C[r][q];
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[c++] = e.eta[r];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) w[c++] = e.J[r][q];
+}
+template <typename T, int N>
+MS_DEVONLY void unpack_elem(const T* w, Elem<T, N>& e) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) e.A[r][q] = w[c++];
+#pragma unroll
+  for (int r = 0; r < N; ++r) e.b[r] = w[c++];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { e.C[r][q] = w[c++]; e.C[q][r] = e.C[r][q]; }
+#pragma unroll
+  for (int r = 0; r < N; ++r) e.eta[r] = w[c++];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { e.J[r][q] = w[c++]; e.J[q][r] = e.J[r][q]; }
+}
 template <typename T, int N>
 MS_DEVONLY void shfl_aff(Aff<T, N>& o, const Aff<T, N>& a, int src) {
   shfl_mat(o.Phi, a.Phi, src);
@@ -322,8 +363,9 @@ template <typename T>
 struct Ws {
   unsigned int* counters;  // two sets of arrival counters (filter, trajectory), zero between launches
   T* lane_pre;             // lane-tiled [ElemSz] per lane: exclusive in-tile filter prefix
-  T* tile_agg;             // [ElemSz][n_tiles]
-  T* tile_carry;           // [Sym + N][n_tiles]  (S, v) before each tile
+  T* tile_agg;             // [ElemSz][n_blocks]  block aggregates
+  T* tile_carry;           // [Sym + N][n_blocks]  (S, v) before each block of four tiles
+  T* tile_pre;             // [ElemSz][n_tiles]  exclusive prefix of each tile inside its block
   T* slane_pre;            // lane-tiled [AffSz] per lane: trajectory map from after the lane's chunk to tile end
   T* stile_agg;            // [AffSz][n_tiles]
   T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
@@ -589,21 +631,21 @@ MS_DEVONLY void release_counter(unsigned int* counters) {
     __hip_atomic_store(counters + threadIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Filter tile scan, run by the last block: (S, v) before every tile.
+// Filter block scan, run by the last block: (S, v) before every block of
+// four tiles, from the block aggregates (plane sets of nt items).
 template <typename T, int N>
-MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
+MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
   __shared__ T s_w[4][ElemSz<N>::n];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
-  const int64_t nt = ws.n_tiles;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
   Elem<T, N> acc, tmp, o, nx_;
   if (t0 < t1) {
-    load_elem(ws.tile_agg, nt, t0, acc);
-    if (t0 + 1 < t1) load_elem(ws.tile_agg, nt, t0 + 1, nx_);
+    load_elem(tile_agg, nt, t0, acc);
+    if (t0 + 1 < t1) load_elem(tile_agg, nt, t0 + 1, nx_);
     for (int64_t t = t0 + 1; t < t1; ++t) {
       o = nx_;
-      if (t + 1 < t1) load_elem(ws.tile_agg, nt, t + 1, nx_);  // one tile ahead
+      if (t + 1 < t1) load_elem(tile_agg, nt, t + 1, nx_);  // one tile ahead
       combine(acc, o, tmp);
       acc = tmp;
     }
@@ -670,13 +712,13 @@ MS_DEVONLY void filter_tile_scan(const Ws<T>& ws) {
   }
   carry_apply(S, v, lx);
   // carries before this thread's tiles (the one after its last tile is not needed)
-  if (t0 + 1 < t1) load_elem(ws.tile_agg, nt, t0, nx_);
+  if (t0 + 1 < t1) load_elem(tile_agg, nt, t0, nx_);
   for (int64_t t = t0; t < t1; ++t) {
-    store_sym(ws.tile_carry, nt, t, S, 0);
-    store_vec(ws.tile_carry, nt, t, v, Sym<N>::n);
+    store_sym(tile_carry, nt, t, S, 0);
+    store_vec(tile_carry, nt, t, v, Sym<N>::n);
     if (t + 1 < t1) {
       o = nx_;
-      if (t + 2 < t1) load_elem(ws.tile_agg, nt, t + 1, nx_);
+      if (t + 2 < t1) load_elem(tile_agg, nt, t + 1, nx_);
       carry_apply(S, v, o);
     }
   }
@@ -939,14 +981,45 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
   }
   shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
   if (lane == 0) elem_identity(o);
-  if (lane == kWave - 1 && tile < ws.n_tiles) store_elem<T, N, true>(ws.tile_agg, ws.n_tiles, tile, agg);
-  const bool last = arrive_last(ws.counters + kCountersFilter);
-  // The lane prefixes are read only by the next kernel, so they are written
-  // after the arrival: the release fence does not wait for them, and they
-  // drain while the last block scans the tiles.
+  // Lane prefixes are read only by the next kernel; written here, they drain
+  // while the block combines its tiles.
   if (g < ws.n_lanes) lt_store_elem(ws.lane_pre, g, o);
+  // The block's four tiles (a0..a3, identities past the last tile) are
+  // combined in a two-level tree: x01 = a0 a1 and x23 = a2 a3, then the block
+  // aggregate x01 x23 (scanned by the last block) and the exclusive prefixes
+  // of the tiles inside the block: 0, a0, x01, x01 a2.
+  __shared__ T s_blk[6][ElemSz<N>::n];
+  const int wv = threadIdx.x >> 6;
+  if (lane == kWave - 1) pack_elem(s_blk[wv], agg);
+  __syncthreads();
+  Elem<T, N> pre;
+  elem_identity(pre);
+  if (wv == 1 || wv == 3) {
+    unpack_elem(s_blk[wv - 1], o);
+    unpack_elem(s_blk[wv], tmp);
+    combine(o, tmp, agg);  // x01 (wave 1), x23 (wave 3)
+    if (lane == 0) pack_elem(s_blk[4 + (wv >> 1)], agg);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    unpack_elem(s_blk[4], o);
+    unpack_elem(s_blk[5], tmp);
+    combine(o, tmp, agg);
+    if (lane == 0) store_elem<T, N, true>(ws.tile_agg, gridDim.x, tile >> 2, agg);
+  } else if (wv == 1) {
+    unpack_elem(s_blk[0], pre);
+  } else if (wv == 2) {
+    unpack_elem(s_blk[4], pre);
+  } else {
+    unpack_elem(s_blk[4], o);
+    unpack_elem(s_blk[2], tmp);
+    combine(o, tmp, pre);
+  }
+  const bool last = arrive_last(ws.counters + kCountersFilter);
+  // tile prefixes: read only by the next kernel, written after the arrival
+  if (lane == 0 && wv > 0 && tile < ws.n_tiles) store_elem(ws.tile_pre, ws.n_tiles, tile, pre);
   if (last) {
-    filter_tile_scan<T, N>(ws);
+    filter_tile_scan<T, N>(ws.tile_agg, ws.tile_carry, int64_t(gridDim.x));
     release_counter(ws.counters + kCountersFilter);
   }
 }
@@ -1023,9 +1096,15 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   T S[N][N], v[N];
   if constexpr (kFilter) {
     if (tile < ws.n_tiles) {
-      load_sym(ws.tile_carry, ws.n_tiles, tile, S, 0);
-      load_vec(ws.tile_carry, ws.n_tiles, tile, v, Sym<N>::n);
+      // block carry, then the tile's prefix inside its block, then the lane's
+      const int64_t nb = (ws.n_tiles + 3) >> 2;
+      load_sym(ws.tile_carry, nb, tile >> 2, S, 0);
+      load_vec(ws.tile_carry, nb, tile >> 2, v, Sym<N>::n);
       Elem<T, N> lp;
+      if (tile & 3) {
+        load_elem(ws.tile_pre, ws.n_tiles, tile, lp);
+        carry_apply(S, v, lp);
+      }
       lt_load_elem(ws.lane_pre, g, lp);
       carry_apply(S, v, lp);
     }
