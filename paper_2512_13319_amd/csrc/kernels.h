@@ -351,6 +351,34 @@ MS_DEVONLY void unpack_elem(const T* w, Elem<T, N>& e) {
     for (int q = 0; q <= r; ++q) { e.J[r][q] = w[c++]; e.J[q][r] = e.J[r][q]; }
 }
 template <typename T, int N>
+MS_DEVONLY void pack_aff(T* w, const Aff<T, N>& a) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) w[c++] = a.Phi[r][q];
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[c++] = a.bt[r];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) w[c++] = a.Om[r][q];
+}
+template <typename T, int N>
+MS_DEVONLY void unpack_aff(const T* w, Aff<T, N>& a) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) a.Phi[r][q] = w[c++];
+#pragma unroll
+  for (int r = 0; r < N; ++r) a.bt[r] = w[c++];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) { a.Om[r][q] = w[c++]; a.Om[q][r] = a.Om[r][q]; }
+}
+template <typename T, int N>
 MS_DEVONLY void shfl_aff(Aff<T, N>& o, const Aff<T, N>& a, int src) {
   shfl_mat(o.Phi, a.Phi, src);
   shfl_vec(o.bt, a.bt, src);
@@ -366,6 +394,7 @@ struct Ws {
   T* tile_agg;             // [ElemSz][n_blocks]  block aggregates
   T* tile_carry;           // [Sym + N][n_blocks]  (S, v) before each block of four tiles
   T* tile_pre;             // [ElemSz][n_tiles]  exclusive prefix of each tile inside its block
+  T* stile_suf;            // [AffSz][n_tiles]  trajectory map from after each tile to the end of its block
   T* slane_pre;            // lane-tiled [AffSz] per lane: trajectory map from after the lane's chunk to tile end
   T* stile_agg;            // [AffSz][n_tiles]
   T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
@@ -724,12 +753,12 @@ MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
   }
 }
 
-// Trajectory tile scan, run by the last block: (x, P) after every tile.
+// Trajectory block scan, run by the last block: (x, P) after every block of
+// four tiles, from the block maps (plane sets of nt items).
 template <typename T, int N>
-MS_DEVONLY void traj_tile_scan(const Ws<T>& ws) {
+MS_DEVONLY void traj_tile_scan(const Ws<T>& ws, int64_t nt) {
   __shared__ T s_w[4][AffSz<N>::n];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
-  const int64_t nt = ws.n_tiles;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
   Aff<T, N> acc, o, nx_;
@@ -1257,12 +1286,46 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
     }
     shfl_aff(o, sagg, lane + 1 < kWave ? lane + 1 : lane);
     if (lane == kWave - 1) aff_identity(o);
-    if (lane == 0 && tile < ws.n_tiles) store_aff<T, N, true>(ws.stile_agg, ws.n_tiles, tile, sagg);
-    const bool last = arrive_last(ws.counters + kCountersTraj);
-    // read only by the next kernel: written after the arrival (see the filter up-sweep)
+    // read only by the next kernel; written here, they drain while the block
+    // combines its tiles
     if (g < ws.n_lanes) lt_store_aff(ws.slane_pre, g, o);
+    // The block's four tile maps (a0..a3, identities past the last tile) are
+    // composed in a two-level tree: x01 = a0 a1 and x23 = a2 a3, then the
+    // block map x01 x23 (scanned by the last block) and the maps from after
+    // each tile to the end of the block: a1 x23, x23, a3, identity.
+    __shared__ T s_tb[6][AffSz<N>::n];
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) pack_aff(s_tb[wv], sagg);
+    __syncthreads();
+    if (wv == 0 || wv == 2) {
+      unpack_aff(s_tb[wv], sagg);
+      unpack_aff(s_tb[wv + 1], o);
+      aff_append(sagg, o);  // x01 (wave 0), x23 (wave 2)
+      if (lane == 0) pack_aff(s_tb[4 + (wv >> 1)], sagg);
+    }
+    __syncthreads();
+    Aff<T, N> suf;
+    int64_t suf_tile = tile;
+    if (wv == 0) {
+      unpack_aff(s_tb[4], sagg);
+      unpack_aff(s_tb[5], o);
+      aff_append(sagg, o);
+      if (lane == 0) store_aff<T, N, true>(ws.stile_agg, gridDim.x, tile >> 2, sagg);
+    } else if (wv == 1) {
+      unpack_aff(s_tb[5], suf);
+    } else if (wv == 2) {
+      unpack_aff(s_tb[3], suf);
+    } else {
+      unpack_aff(s_tb[1], suf);  // tile 0 of the block: a1 x23
+      unpack_aff(s_tb[5], o);
+      aff_append(suf, o);
+      suf_tile = tile - 3;
+    }
+    const bool last = arrive_last(ws.counters + kCountersTraj);
+    // read only by the next kernel: written after the arrival
+    if (lane == 0 && wv > 0 && suf_tile < ws.n_tiles) store_aff(ws.stile_suf, ws.n_tiles, suf_tile, suf);
     if (last) {
-      traj_tile_scan<T, N>(ws);
+      traj_tile_scan<T, N>(ws, int64_t(gridDim.x));
       release_counter(ws.counters + kCountersTraj);
     }
   }
@@ -1322,9 +1385,16 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
   TS* Po = static_cast<TS*>(to.Ps);
   T x[N], P[N][N];
   if (tile < ws.n_tiles) {
-    load_vec(ws.stile_carry, ws.n_tiles, tile, x, 0);
-    load_sym(ws.stile_carry, ws.n_tiles, tile, P, N);
+    // value after the tile's block, through the tiles after it in the block,
+    // then through the lanes after this one in the tile
+    const int64_t nb = (ws.n_tiles + 3) >> 2;
+    load_vec(ws.stile_carry, nb, tile >> 2, x, 0);
+    load_sym(ws.stile_carry, nb, tile >> 2, P, N);
     Aff<T, N> lp;
+    if ((tile & 3) != 3) {
+      load_aff(ws.stile_suf, ws.n_tiles, tile, lp);
+      aff_apply(lp, x, P);
+    }
     lt_load_aff(ws.slane_pre, g, lp);
     aff_apply(lp, x, P);
   }

@@ -11,7 +11,7 @@ namespace ms {
 struct WsLayout {
   int64_t n_lanes;   // padded to whole tiles
   int64_t n_tiles;
-  size_t off[8];     // counters, lane_pre, tile_agg, tile_carry, slane_pre, stile_agg, stile_carry, tile_pre
+  size_t off[9];     // counters, lane_pre, tile_agg, tile_carry, slane_pre, stile_agg, stile_carry, tile_pre, stile_suf
   size_t total;
 };
 
@@ -46,16 +46,17 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   // flagged backward-filter runs (two-filter form)
   const int64_t rlane = aff > elem + 1 ? aff : elem + 1;
   const int64_t rcarry = nx + sym > elem ? nx + sym : elem;
-  const size_t sizes[8] = {256,
+  const size_t sizes[9] = {256,
                            size_t(elem * w.n_lanes) * sz,
                            size_t(elem * w.n_tiles) * sz,
                            size_t((sym + nx) * w.n_tiles) * sz,
                            size_t(rlane * w.n_lanes) * sz,
                            size_t(rlane * w.n_tiles) * sz,
                            size_t(rcarry * w.n_tiles) * sz,
-                           size_t(elem * w.n_tiles) * sz};
+                           size_t(elem * w.n_tiles) * sz,
+                           size_t(aff * w.n_tiles) * sz};
   size_t o = 0;
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 9; ++i) {
     w.off[i] = o;
     o += align256(sizes[i]);
   }

@@ -52,6 +52,7 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk) {
   w.stile_agg = reinterpret_cast<T*>(b + l.off[5]);
   w.stile_carry = reinterpret_cast<T*>(b + l.off[6]);
   w.tile_pre = reinterpret_cast<T*>(b + l.off[7]);
+  w.stile_suf = reinterpret_cast<T*>(b + l.off[8]);
   w.n_lanes = l.n_lanes;
   w.n_tiles = l.n_tiles;
   w.chunk = chunk;
