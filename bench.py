@@ -81,27 +81,41 @@ def kernel_bytes(nx, ny, s, kind):
 
 
 def roofline_for(kern, rec, fresh, n_states, nx, ny, s, dtype):
-    """Roofline object of the longest kernel in `kern` {name: (count, ms)}:
-    against the FP64 VALU roof when the counter record has its flop count on
-    this workload, else against HBM with its algorithmic bytes."""
+    """Roofline object of the longest kernel in `kern` {name: (count, ms)}.
+
+    The bound is the roof the kernel's arithmetic intensity puts it under:
+    counted FP64 flops per algorithmic HBM byte against the ridge point
+    78.6 TFLOP/s / 8 TB/s (9.8 flop/B). Below the ridge the kernel is priced
+    against HBM with its algorithmic bytes, above it against the FP64 vector
+    roof with its counted flops. Without a flop count for this workload it is
+    priced against HBM."""
     dom = max((k for k in kern if k != "aux"), key=lambda k: kern[k][1])
     dom_ms = kern[dom][1]
-    bytes_dom = kernel_bytes(nx, ny, s, dom) * n_states
+    bytes_state = kernel_bytes(nx, ny, s, dom)
+    bytes_dom = bytes_state * n_states
     hbm_gbs = bytes_dom / (dom_ms * 1e-3) / 1e9
     kc = (rec or {}).get("kernels", {}).get(dom)
-    if kc is not None and kc.get("n_states") == n_states:
+    counted = kc is not None and kc.get("n_states") == n_states
+    ridge = VALU_PEAK_TFLOPS[dtype] * 1e3 / HBM_PEAK_GBS
+    intensity = kc["flops_fp64_per_state"] / bytes_state if counted else None
+    if counted and intensity >= ridge:
         # FP64 VALU roof: the per-state flop count of the kernel (counted, see
         # the counter record) over its measured launch duration
         flops = kc["flops_fp64_per_state"] * n_states
         achieved = flops / (dom_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS[dtype],
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS[dtype], 4),
-                "traffic": kc["hbm_bytes"] if fresh else None,
-                "flops_per_state": kc["flops_fp64_per_state"],
-                "counters_current": fresh}
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS[dtype], 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = kc["hbm_bytes"] if counted and fresh else None
+    if counted:
+        roof.update({"flops_per_state": kc["flops_fp64_per_state"],
+                     "intensity_flop_per_byte": round(intensity, 2),
+                     "ridge_flop_per_byte": round(ridge, 2),
+                     "fp64_achieved_TFLOPs": round(kc["flops_fp64_per_state"] * n_states
+                                                   / (dom_ms * 1e-3) / 1e12, 3),
+                     "counters_current": fresh})
     roof.update({
         "kernel": dom, "kernel_ms": round(dom_ms, 4),
         "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
