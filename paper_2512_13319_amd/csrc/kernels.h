@@ -831,33 +831,34 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws, int64_t nt) {
   }
 }
 
-// Backward-filter tile scan of the two-filter smoother, run by the last
-// block: for every tile, the run after it up to the next segment start
-// (segmented reverse scan, see seg_append).  Tile aggregates carry their flag
-// as component ElemSz of the plane set.
+// A flagged run (element plus segment-start flag): the flag is component
+// ElemSz of the plane set.
 template <typename T, int N>
 MS_DEVONLY void load_selem(const T* base, int64_t ld, int64_t i, Elem<T, N>& e, T& f) {
   load_elem(base, ld, i, e);
   f = base[ElemSz<N>::n * ld + i];
 }
 
+// Backward-filter block scan of the two-filter smoother, run by the last
+// block: for every block of four tiles, the run after it up to the next
+// segment start (segmented reverse scan, see seg_append), from the block runs
+// (plane sets of nt flagged items).
 template <typename T, int N>
-MS_DEVONLY void suffix_tile_scan(const Ws<T>& ws) {
+MS_DEVONLY void suffix_tile_scan(const T* agg, T* carry, int64_t nt) {
   constexpr int E = ElemSz<N>::n;
   __shared__ T s_w[4][E + 1];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
-  const int64_t nt = ws.n_tiles;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
   Elem<T, N> acc, o, nx_;
   T af = T(0), of = T(0), nf = T(0);
   if (t0 < t1) {
-    load_selem(ws.stile_agg, nt, t0, acc, af);
-    if (t0 + 1 < t1) load_selem(ws.stile_agg, nt, t0 + 1, nx_, nf);
+    load_selem(agg, nt, t0, acc, af);
+    if (t0 + 1 < t1) load_selem(agg, nt, t0 + 1, nx_, nf);
     for (int64_t t = t0 + 1; t < t1; ++t) {
       o = nx_;
       of = nf;
-      if (t + 1 < t1) load_selem(ws.stile_agg, nt, t + 1, nx_, nf);  // one tile ahead
+      if (t + 1 < t1) load_selem(agg, nt, t + 1, nx_, nf);  // one tile ahead
       seg_append(acc, af, o, of);
     }
   } else {
@@ -925,13 +926,13 @@ MS_DEVONLY void suffix_tile_scan(const Ws<T>& ws) {
   }
   // runs after each of this thread's tiles, right to left (the one before
   // its first tile is not needed)
-  if (t1 - 1 > t0) load_selem(ws.stile_agg, nt, t1 - 1, nx_, nf);
+  if (t1 - 1 > t0) load_selem(agg, nt, t1 - 1, nx_, nf);
   for (int64_t t = t1 - 1; t >= t0; --t) {
-    store_elem(ws.stile_carry, nt, t, ex);
+    store_elem(carry, nt, t, ex);
     if (t > t0) {
       o = nx_;
       of = nf;
-      if (t - 1 > t0) load_selem(ws.stile_agg, nt, t - 1, nx_, nf);
+      if (t - 1 > t0) load_selem(agg, nt, t - 1, nx_, nf);
       // ex <- tile t (+) ex
       T f2 = of;
       seg_append(o, f2, ex, exf);
@@ -1011,7 +1012,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
   shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
   if (lane == 0) elem_identity(o);
   // Lane prefixes are read only by the next kernel; written here, they drain
-  // while the block combines its tiles.
+  // while the block combines its tiles (measured: faster than holding them
+  // in LDS and storing them after the arrival).
   if (g < ws.n_lanes) lt_store_elem(ws.lane_pre, g, o);
   // The block's four tiles (a0..a3, identities past the last tile) are
   // combined in a two-level tree: x01 = a0 a1 and x23 = a2 a3, then the block
@@ -1346,15 +1348,63 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
       elem_identity(o);
       of = T(0);
     }
-    if (lane == 0 && tile < ws.n_tiles) {
-      store_elem<T, N, true>(ws.stile_agg, ws.n_tiles, tile, pagg);
-      wt_store(&ws.stile_agg[ElemSz<N>::n * ws.n_tiles + tile], pf);
+    // The lane runs are read only by the next kernel; written here, they
+    // drain while the block joins its tiles.
+    constexpr int E = ElemSz<N>::n;
+    if (g < ws.n_lanes) lt_store_elem<T, N, true>(ws.slane_pre, g, o, of);
+    // The block's four tile runs (a0..a3 with their flags; identities with
+    // no segment start past the last tile) are joined in a two-level tree:
+    // x01 = a0 (+) a1 and x23 = a2 (+) a3, then the block run x01 (+) x23
+    // (scanned by the last block) and the runs from after each tile to the
+    // end of the block: a1 (+) x23, x23, a3, empty.
+    __shared__ T s_tb[6][E + 1];
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) {
+      pack_elem(s_tb[wv], pagg);
+      s_tb[wv][E] = pf;
+    }
+    __syncthreads();
+    if (wv == 0 || wv == 2) {
+      unpack_elem(s_tb[wv + 1], o);
+      seg_append(pagg, pf, o, s_tb[wv + 1][E]);  // x01 (wave 0), x23 (wave 2)
+      if (lane == 0) {
+        pack_elem(s_tb[4 + (wv >> 1)], pagg);
+        s_tb[4 + (wv >> 1)][E] = pf;
+      }
+    }
+    __syncthreads();
+    Elem<T, N> suf;
+    T sf = T(0);
+    int64_t suf_tile = tile;
+    if (wv == 0) {
+      unpack_elem(s_tb[5], o);
+      seg_append(pagg, pf, o, s_tb[5][E]);
+      if (lane == 0) {
+        const int64_t nb = gridDim.x;
+        store_elem<T, N, true>(ws.stile_agg, nb, tile >> 2, pagg);
+        wt_store(&ws.stile_agg[E * nb + (tile >> 2)], pf);
+      }
+    } else if (wv == 1) {
+      unpack_elem(s_tb[5], suf);
+      sf = s_tb[5][E];
+    } else if (wv == 2) {
+      unpack_elem(s_tb[3], suf);
+      sf = s_tb[3][E];
+    } else {
+      unpack_elem(s_tb[1], suf);  // tile 0 of the block: a1 (+) x23
+      sf = s_tb[1][E];
+      unpack_elem(s_tb[5], o);
+      seg_append(suf, sf, o, s_tb[5][E]);
+      suf_tile = tile - 3;
     }
     const bool last = arrive_last(ws.counters + kCountersTraj);
-    // read only by the next kernel: written after the arrival (see the filter up-sweep)
-    if (g < ws.n_lanes) lt_store_elem<T, N, true>(ws.slane_pre, g, o, of);
+    // in-block runs: read only by the next kernel, written after the arrival
+    if (lane == 0 && wv > 0 && suf_tile < ws.n_tiles) {
+      store_elem(ws.stile_suf, ws.n_tiles, suf_tile, suf);
+      ws.stile_suf[E * ws.n_tiles + suf_tile] = sf;
+    }
     if (last) {
-      suffix_tile_scan<T, N>(ws);
+      suffix_tile_scan<T, N>(ws.stile_agg, ws.stile_carry, int64_t(gridDim.x));
       release_counter(ws.counters + kCountersTraj);
     }
   }
@@ -1655,15 +1705,21 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
   TS* Po = static_cast<TS*>(to.Ps);
   const int64_t j1 = lane_end(g, ws.n_lanes, ns, ws.chunk);
   if (j0 >= j1) return;
-  // the run after the chunk: in-tile part, then (unless it reached a
-  // segment start) the tile's
+  // the run after the chunk: in-tile part, then (each unless the run so far
+  // reached a segment start) the rest of the block's, then the block's
   Elem<T, N> s;
   {
     T f;
     lt_load_elem<T, N, true>(ws.slane_pre, g, s, &f);
+    Elem<T, N> c, t;
+    if (f == T(0) && (tile & 3) != 3) {
+      // the rest of the block after this tile (the last tile of a block has none)
+      load_selem(ws.stile_suf, ws.n_tiles, tile, c, f);
+      combine(s, c, t);
+      s = t;
+    }
     if (f == T(0)) {
-      Elem<T, N> c, t;
-      load_elem(ws.stile_carry, ws.n_tiles, tile, c);
+      load_elem(ws.stile_carry, (ws.n_tiles + 3) >> 2, tile >> 2, c);
       combine(s, c, t);
       s = t;
     }

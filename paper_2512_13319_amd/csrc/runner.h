@@ -54,7 +54,7 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
                            size_t(rlane * w.n_tiles) * sz,
                            size_t(rcarry * w.n_tiles) * sz,
                            size_t(elem * w.n_tiles) * sz,
-                           size_t(aff * w.n_tiles) * sz};
+                           size_t(rlane * w.n_tiles) * sz};
   size_t o = 0;
   for (int i = 0; i < 9; ++i) {
     w.off[i] = o;

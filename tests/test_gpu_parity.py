@@ -72,6 +72,9 @@ CASES = {
     # them inside a tile
     "batched_empty_segments": lambda: workloads.cv_batched(lens=[0, 1500, 0, 0, 533, 0, 1, 0],
                                                            seed=19),
+    # ~1e5 states in 120 segments of 32..4096 steps: 25 to 100 blocks of four
+    # tiles, segments that span several blocks and blocks with several starts
+    "batched_many_blocks": lambda: workloads.cv_batched(n_seg=120, lmin=5.0, lmax=12.0, seed=20),
 }
 
 

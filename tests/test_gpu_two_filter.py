@@ -57,7 +57,7 @@ def test_two_filter_parity(case, dtype):
 
 @pytest.mark.parametrize("chunk", [8, 16])
 @pytest.mark.parametrize("case", ["batched_tail_heads", "cv_tail8_merged", "linear_tv",
-                                  "lorenz_fixed_xbar"])
+                                  "lorenz_fixed_xbar", "batched_many_blocks"])
 def test_two_filter_parity_schedules(case, chunk):
     _check(case, "f64", chunk)
 
