@@ -147,6 +147,10 @@ def main():
                     help="skip the exact-discretisation (linear-model path) measurement")
     ap.add_argument("--no-ct", action="store_true",
                     help="skip the coordinated-turn (iterated nonlinear) measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched ragged-segment measurement (4096 segments)")
+    ap.add_argument("--cpu-sample-segs", type=int, default=256,
+                    help="segments of the batched CPU-baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -308,6 +312,10 @@ def main():
     if not args.no_ct:
         ct_res, wl_ct = measure_ct(args, ms, _lib, lib, timed, tdt, s)
         res["coordinated_turn"] = ct_res
+    bt_res = None
+    if not args.no_batched:
+        bt_res, wl_bt = measure_batched(args, ms, _lib, lib, timed)
+        res["batched"] = bt_res
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
         if two_filter is not None:
@@ -316,6 +324,8 @@ def main():
             ct_res["cpu_baseline"] = cpu_baseline_ct(wl_ct, args.cpu_sample_ct)
         if ex_res is not None:
             ex_res["cpu_baseline"] = cpu_baseline_exact(wl_ex, args.cpu_sample_tf)
+        if bt_res is not None:
+            bt_res["cpu_baseline"] = cpu_baseline_batched(wl_bt, args.cpu_sample_segs)
     print(json.dumps(res))
 
 
@@ -386,6 +396,79 @@ def measure_ct(args, ms, _lib, lib, timed, tdt, s):
            "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
            "roofline": roof}
     return res, wl
+
+
+def measure_batched(args, ms, _lib, lib, timed):
+    """Batched segmented scan: 4096 independent constant-velocity tracks of
+    ragged lengths floor(2^U(8, 14)) (about 1.6e7 steps) in one launch
+    sequence, FP32 storage; per-segment log-likelihood, objective and their
+    gradients in (gamma, q, r), smoothed x*, P^s."""
+    import torch
+
+    import workloads
+
+    wl = workloads.config(4).rounded("f32")
+    p = ms.problem_from_workload(wl, dtype=torch.float32, device="cuda:0")
+    if not args.no_autotune:
+        ms.autotune(p)
+    f64 = torch.float64
+    n = p.n_seg
+    out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx), Ps=p._tiled(p.nsym),
+               loglik=p._empty(n, dtype=f64), obj=p._empty(n, dtype=f64),
+               g_loglik=p._empty(n, 3, dtype=f64), g_obj=p._empty(n, 3, dtype=f64))
+
+    def step():
+        ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True, out=out,
+                  natural=False)
+
+    ms_e, _, kern = timed(step, args.steps, args.warmup, True)
+    if args.no_graph:
+        ms_g = ms_e
+    else:
+        g = ms.GraphedSmooth(p, covariances=True, loglik=True, objective=True, grad=True)
+        ms_g, _, _ = timed(g.replay, args.steps, args.warmup, False)
+    rec, fresh = counter_record("f32", "cv4_batched4096")
+    res = {"value": wl.n_steps / (ms_g * 1e-3), "unit": "time-steps/s", "ms_per_step": ms_g,
+           "eager_ms_per_step": round(ms_e, 4),
+           "workload": "4096 independent 2-D constant-velocity tracks, lengths "
+                       "floor(2^U(8,14)) steps (%d steps in all), q ~ U[0.1,1], r ~ U[0.01,0.2], "
+                       "dt=1e-3, FP32 storage; per-segment x*, P^s, log-likelihood, objective "
+                       "and adjoint d/d(gamma,q,r)" % wl.n_steps,
+           "n_seg": int(n), "n_steps": int(wl.n_steps), "storage": "f32",
+           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, 4, "f32")}
+    return res, wl
+
+
+def cpu_baseline_batched(wl, n_segs):
+    """The plain-C sequential oracle (covariance Kalman filter + RTS smoother +
+    likelihood + objective, no gradients) on the first n_segs segments, one
+    thread."""
+    from oracle import cref
+
+    sub = first_segments(wl, n_segs)
+    t0 = time.perf_counter()
+    cref.smooth(sub)
+    dt = time.perf_counter() - t0
+    n = int(sub.n_steps)
+    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the 4096 segments (%d steps): sequential C Kalman filter + "
+                      "RTS smoother + log-likelihood + objective (no gradients), FP64, %.1f s"
+                      % (n_segs, n, dt), "cpu": cpu_info()}
+
+
+def first_segments(wl, n):
+    """The first n segments of a batched workload (any lengths)."""
+    import workloads
+
+    k = int(wl.seg_off[n])
+    sub = workloads.Workload(**{**wl.__dict__})
+    sub.seg_off = wl.seg_off[:n + 1].copy()
+    sub.dt = wl.dt[:k] if len(wl.dt) > 1 else wl.dt
+    sub.y = wl.y[:, :k]
+    sub.theta, sub.m0, sub.P0 = wl.theta[:n], wl.m0[:n], wl.P0[:n]
+    sub.x_true = wl.x_true[:, :k + n]
+    return sub
 
 
 def exact_terms_cv(q, gamma=0.0):

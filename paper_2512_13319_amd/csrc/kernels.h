@@ -569,12 +569,21 @@ struct Cursor {
 };
 
 // --------------------------------------------------------------------------- reductions
-// Segmented sum over the lanes of a wavefront (segment ids non-decreasing
-// with the lane index), then one atomic per run.  seg < 0 marks no data.
+// Segmented sum over the lanes of a block (segment ids non-decreasing with the
+// thread index; seg < 0 marks no data), added atomically into dst[t][seg *
+// stride[t]].  Each wavefront sums its runs; a run that starts inside a
+// wavefront is added by its first lane, and the run that starts at lane 0 goes
+// through LDS, where one thread joins those of consecutive wavefronts in the
+// same segment before adding them.  Atomics on one address are serialised at
+// the memory side: with long segments, one atomic per wavefront on each
+// accumulator kept the trajectory fix-up waiting for ~30 us after its last
+// state; one per block cost ~1.5 us.  Every thread of the block calls it.
 template <int K>
-MS_DEVONLY void flush_wave(int64_t seg, double (&val)[K], double* const (&dst)[K],
-                           const int64_t (&stride)[K]) {
-  const int lane = threadIdx.x & (kWave - 1);
+MS_DEVONLY void flush_block(int64_t seg, double (&val)[K], double* const (&dst)[K],
+                            const int64_t (&stride)[K]) {
+  __shared__ double s_val[kBlock / kWave][K];
+  __shared__ int s_seg[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
   const int sg = int(seg);
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
   for (int d = 1; d < kWave; d <<= 1) {
@@ -587,10 +596,32 @@ MS_DEVONLY void flush_wave(int64_t seg, double (&val)[K], double* const (&dst)[K
     }
   }
   const int sp = shfl(sg, lane > 0 ? lane - 1 : 0);
-  if (sg >= 0 && (lane == 0 || sp != sg)) {
+  if (lane == 0) {
+    s_seg[wv] = sg;
+#pragma unroll
+    for (int t = 0; t < K; ++t) s_val[wv][t] = sg >= 0 ? val[t] : 0.0;
+  } else if (sg >= 0 && sp != sg) {
 #pragma unroll
     for (int t = 0; t < K; ++t)
       if (dst[t]) unsafeAtomicAdd(dst[t] + sg * stride[t], val[t]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      if (!dst[t]) continue;
+      int cur = -1;
+      double a = 0.0;
+      for (int w = 0; w < kBlock / kWave; ++w) {
+        if (s_seg[w] != cur) {
+          if (cur >= 0) unsafeAtomicAdd(dst[t] + cur * stride[t], a);
+          cur = s_seg[w];
+          a = 0.0;
+        }
+        a += s_val[w][t];
+      }
+      if (cur >= 0) unsafeAtomicAdd(dst[t] + cur * stride[t], a);
+    }
   }
 }
 
@@ -1275,7 +1306,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
       double* d[1] = {acc.loglik};
       const int64_t sd[1] = {1};
       double val[1] = {ll};
-      flush_wave<1>(seg_acc, val, d, sd);
+      flush_block<1>(seg_acc, val, d, sd);
     }
   }
   if constexpr (kTraj) {
@@ -1683,7 +1714,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       q0 = q1;
     }
   }
-  if (to.want_obj || kGrad) flush_wave<KV>(seg_acc, val, dst, dstr);
+  if (to.want_obj || kGrad) flush_block<KV>(seg_acc, val, dst, dstr);
 }
 
 // --------------------------------------------------------------------------- pass C'
