@@ -27,6 +27,7 @@
 // segment's last state carries the constant trajectory map (0, S^{-1} v,
 // S^{-1}), which cuts the reverse scan.
 #pragma once
+#include "counters.h"
 #include "elements.h"
 
 namespace ms {
@@ -643,7 +644,7 @@ MS_DEVONLY void flush_lane(int64_t seg, double (&val)[K], double* const (&dst)[K
 // Each device-scope atomic on one address is serialised at the memory side,
 // so 256 blocks on a single counter put ~20 us of queueing in front of the
 // last arrival; groups of 32 contend in parallel and only 8 reach the top.
-// counters[0..7]: groups, counters[8]: top.
+// Counter layout: counters.h (each counter on a cache line of its own).
 //
 // Ordering.  Everything the last block reads (the tile aggregates) is written
 // with device-coherent stores (wt_store: past the XCD's non-coherent L2), so a
@@ -654,9 +655,6 @@ MS_DEVONLY void flush_lane(int64_t seg, double (&val)[K], double* const (&dst)[K
 // L2 write-back (buffer_wbl2) per wavefront, which measured 10-30 us each here
 // and is only needed for ordinary (write-back) stores, of which the data read
 // across blocks has none.
-constexpr int kArriveGroups = 8;
-constexpr int kArriveWords = kArriveGroups + 1;
-constexpr int kCountersFilter = 0, kCountersTraj = 16;  // word offsets (64 words are cleared)
 
 MS_DEVONLY bool arrive_last(unsigned int* counters) {
   __shared__ unsigned int s_last;
@@ -667,10 +665,10 @@ MS_DEVONLY bool arrive_last(unsigned int* counters) {
     const unsigned gsize = nb / kArriveGroups + (grp < nb % kArriveGroups ? 1u : 0u);
     const unsigned ngroups = nb < unsigned(kArriveGroups) ? nb : unsigned(kArriveGroups);
     unsigned last = 0;
-    const unsigned t =
-        __hip_atomic_fetch_add(counters + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned t = __hip_atomic_fetch_add(counters + grp * kArriveStride, 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
     if (t == gsize - 1) {
-      const unsigned u = __hip_atomic_fetch_add(counters + kArriveGroups, 1u, __ATOMIC_RELAXED,
+      const unsigned u = __hip_atomic_fetch_add(counters + kArriveGroups * kArriveStride, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
       last = (u == ngroups - 1) ? 1u : 0u;
     }
@@ -688,7 +686,8 @@ MS_DEVONLY bool arrive_last(unsigned int* counters) {
 // Reset by the last block once every block has arrived.
 MS_DEVONLY void release_counter(unsigned int* counters) {
   if (threadIdx.x < kArriveWords)
-    __hip_atomic_store(counters + threadIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(counters + threadIdx.x * kArriveStride, 0u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Filter block scan, run by the last block: (S, v) before every block of

@@ -18,7 +18,7 @@
 namespace ms {
 
 __global__ void k_clear_words(unsigned int* w, int n) {
-  if (int(threadIdx.x) < n) w[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
 }
 
 // ---------------------------------------------------------------- profiling hook
@@ -303,8 +303,10 @@ size_t map_workspace_bytes(const map_problem* p) {
 }
 
 map_status map_workspace_init(void* ws, size_t ws_bytes, void* stream) {
-  if (ws == nullptr || ws_bytes < 256) return fail(MAP_E_WORKSPACE, "workspace too small");
-  k_clear_words<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(static_cast<unsigned int*>(ws), 64);
+  if (ws == nullptr || ws_bytes < size_t(kCounterWords) * 4)
+    return fail(MAP_E_WORKSPACE, "workspace too small");
+  k_clear_words<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(static_cast<unsigned int*>(ws),
+                                                                   kCounterWords);
   return hip_status(hipGetLastError(), "map_workspace_init");
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/mapscan.h"
+#include "counters.h"
 
 namespace ms {
 
@@ -46,7 +47,7 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   // flagged backward-filter runs (two-filter form)
   const int64_t rlane = aff > elem + 1 ? aff : elem + 1;
   const int64_t rcarry = nx + sym > elem ? nx + sym : elem;
-  const size_t sizes[9] = {256,
+  const size_t sizes[9] = {size_t(kCounterWords) * 4,
                            size_t(elem * w.n_lanes) * sz,
                            size_t(elem * w.n_tiles) * sz,
                            size_t((sym + nx) * w.n_tiles) * sz,
