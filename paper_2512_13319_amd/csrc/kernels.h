@@ -178,6 +178,28 @@ MS_DEVONLY void tload_vec(const P* base, int C, int64_t i, T (&a)[N], int c0 = 0
 #pragma unroll
   for (int r = 0; r < N; ++r) a[r] = T(base[tix(i, c0 + r, C)]);
 }
+// raw components in the storage type (prefetch buffers), converted where used
+template <typename P, int K>
+MS_DEVONLY void tload_raw(const P* base, int C, int64_t i, P (&a)[K], int c0 = 0) {
+#pragma unroll
+  for (int r = 0; r < K; ++r) a[r] = base[tix(i, c0 + r, C)];
+}
+template <typename P, typename T, int N>
+MS_DEVONLY void sym_from_raw(const P (&a)[Sym<N>::n], T (&m)[N][N]) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) {
+      m[r][q] = T(a[c++]);
+      m[q][r] = m[r][q];
+    }
+}
+template <typename P, typename T, int K>
+MS_DEVONLY void vec_from_raw(const P (&a)[K], T (&o)[K]) {
+#pragma unroll
+  for (int r = 0; r < K; ++r) o[r] = T(a[r]);
+}
 template <typename P, typename T, int N, int M>
 MS_DEVONLY void tstore_mat(P* base, int C, int64_t i, const T (&a)[N][M], int c0 = 0) {
 #pragma unroll
@@ -455,32 +477,38 @@ struct Cursor {
 
   // The per-state inputs of the step that ends at state i (measurement, step
   // length, linearisation state).  Loads only, so that a loop can issue them
-  // one state ahead of their use; valid for any i < n_states (the values of a
-  // segment's first state are simply not used).
+  // ahead of their use; valid for any i < n_states (the values of a segment's
+  // first state are simply not used).  They stay in the storage type until
+  // used: a conversion on arrival would make the loop wait for the load there,
+  // and would double the registers of FP32 storage.
   struct Raw {
-    T dt;
-    T y[NY];
-    T xb[M::kNonlinear ? NX : 1];
+    TS dt;
+    TS y[NY];
+    TS xb[M::kNonlinear ? NX : 1];
+    MS_DEVONLY void meas(T (&o)[NY]) const {
+#pragma unroll
+      for (int c = 0; c < NY; ++c) o[c] = T(y[c]);
+    }
   };
   MS_DEVONLY void fetch(const Prob<TS>& p, int64_t i, Raw& r) const {
-    r.dt = T(p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0]);
+    r.dt = p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0];
 #pragma unroll
-    for (int c = 0; c < NY; ++c) r.y[c] = T(p.y[tix(i, c, NY)]);
+    for (int c = 0; c < NY; ++c) r.y[c] = p.y[tix(i, c, NY)];
     if constexpr (M::kNonlinear) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) r.xb[c] = T(p.xbar[tix(i, c, NX)]);
+      for (int c = 0; c < NX; ++c) r.xb[c] = p.xbar[tix(i, c, NX)];
     }
   }
 
   // Model terms of the step that ends at (non-head) state i from its fetched inputs.
   MS_DEVONLY void terms(const Prob<TS>& p, int64_t i, const Raw& r, Step<T, NX, NY, NW>& st) const {
     const int64_t k = i - s - 1;  // step index
-    const T dt = r.dt;
+    const T dt = T(r.dt);
     if constexpr (M::NTH > 0) {
       T xb[NX];
       if constexpr (M::kNonlinear) {
 #pragma unroll
-        for (int c = 0; c < NX; ++c) xb[c] = r.xb[c];
+        for (int c = 0; c < NX; ++c) xb[c] = T(r.xb[c]);
       } else {
 #pragma unroll
         for (int c = 0; c < NX; ++c) xb[c] = T(0);
@@ -490,7 +518,8 @@ struct Cursor {
         // angular component: the residual y - r modulo 2 pi into [-pi, pi),
         // i.e. the measurement taken on the branch nearest the prediction
         constexpr int a = M::kAngle;
-        st.r[a] = r.y[a] - wrap_angle(r.y[a] - st.r[a]);
+        const T ya = T(r.y[a]);
+        st.r[a] = ya - wrap_angle(ya - st.r[a]);
       }
     } else {
       st.dt = dt;
@@ -539,8 +568,7 @@ struct Cursor {
     Raw r;
     fetch(p, i, r);
     terms(p, i, r, st);
-#pragma unroll
-    for (int c = 0; c < NY; ++c) y[c] = r.y[c];
+    r.meas(y);
   }
 
   MS_DEVONLY void xbar(const Prob<TS>& p, int64_t i, T (&xb)[NX]) const {
@@ -1022,8 +1050,10 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
       } else {
         Step<T, N, M::NY, M::NW> st;
         cur.terms(p, i, rc, st);
+        T y[M::NY];
+        rc.meas(y);
         Fresh<T, N, M::NW> f;
-        fresh_from_step(st, rc.y, f);
+        fresh_from_step(st, y, f);
         fold_fresh(agg, f);
       }
       if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
@@ -1220,7 +1250,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           if constexpr (kSuf) pf = T(1);
         } else {
           Step<T, N, NY, NW> st;
-          const T(&y)[NY] = rc.y;
+          T y[NY];
+          rc.meas(y);
           cur.terms(p, i, rc, st);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
@@ -1269,8 +1300,10 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         } else {
           Step<T, N, NY, NW> st;
           cur.terms(p, i + 1, rc, st);
+          T y[NY];
+          rc.meas(y);
           Fresh<T, N, NW> f;
-          fresh_from_step(st, rc.y, f);
+          fresh_from_step(st, y, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           aff_append(sagg, G, beta, Lam);
@@ -1292,8 +1325,10 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         // iteration
         Step<T, N, NY, NW> st;
         cur.terms(p, il + 1, rn, st);
+        T y[NY];
+        rn.meas(y);
         Fresh<T, N, NW> f;
-        fresh_from_step(st, rn.y, f);
+        fresh_from_step(st, y, f);
         T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
         info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
         aff_append(sagg, G, beta, Lam);
@@ -1506,14 +1541,14 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     // only after its last use, so the loop carries it in the same registers
     // (a register copy of a buffer would make its loads wait early).
     struct Ahead {
-      T S[N][N];
-      T v[N];
+      TS S[Sym<N>::n];
+      TS v[N];
       typename Cursor<TS, T, M>::Raw r;
     } q0, q1, q2;
     auto refill = [&](int64_t k, Ahead& q) {
       const int64_t ia = k >= j0 ? k : j0;
-      tload_sym(Si, Sym<N>::n, ia, q.S);
-      tload_vec(vi, N, ia, q.v);
+      tload_raw(Si, Sym<N>::n, ia, q.S);
+      tload_raw(vi, N, ia, q.v);
       cur.fetch(p, ia + 1 < ns ? ia + 1 : ia, q.r);
     };
     refill(il, q0);
@@ -1522,16 +1557,16 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     // one state of the backward walk; q holds state i
     auto body = [&](int64_t i, Ahead& q) {
       T S[N][N], v[N];
-      mcopy(q.S, S);
-#pragma unroll
-      for (int a = 0; a < N; ++a) v[a] = q.v[a];
+      sym_from_raw<TS, T, N>(q.S, S);
+      vec_from_raw(q.v, v);
       const typename Cursor<TS, T, M>::Raw rc = q.r;
       if (cur.is_last(i)) {
         spd_inv(S, P);
         mv(P, v, x);
       } else {
         Step<T, N, NY, NW> st;
-        const T(&y)[NY] = rc.y;
+        T y[NY];
+        rc.meas(y);
         cur.terms(p, i + 1, rc, st);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
@@ -1659,7 +1694,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
             T xb[N];
             if constexpr (M::kNonlinear) {
 #pragma unroll
-              for (int a = 0; a < N; ++a) xb[a] = rc.xb[a];
+              for (int a = 0; a < N; ++a) xb[a] = T(rc.xb[a]);
             } else {
 #pragma unroll
               for (int a = 0; a < N; ++a) xb[a] = T(0);
@@ -1760,14 +1795,14 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
   // filter moments and step inputs of a state, in three rotating buffers
   // refilled three states ahead (as in the trajectory fix-up)
   struct Ahead {
-    T S[N][N];
-    T v[N];
+    TS S[Sym<N>::n];
+    TS v[N];
     typename Cursor<TS, T, M>::Raw r;
   } q0, q1, q2;
   auto refill = [&](int64_t k, Ahead& q) {
     const int64_t ia = k >= j0 ? k : j0;
-    tload_sym(Si, Sym<N>::n, ia, q.S);
-    tload_vec(vi, N, ia, q.v);
+    tload_raw(Si, Sym<N>::n, ia, q.S);
+    tload_raw(vi, N, ia, q.v);
     cur.fetch(p, ia, q.r);
   };
   refill(il, q0);
@@ -1775,7 +1810,10 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
   refill(il - 2, q2);
   auto body = [&](int64_t i, Ahead& q) {
     T x[N], P[N][N];
-    two_filter_point<T, N, kCov>(q.S, q.v, s, x, P);
+    T S[N][N], v[N];
+    sym_from_raw<TS, T, N>(q.S, S);
+    vec_from_raw(q.v, v);
+    two_filter_point<T, N, kCov>(S, v, s, x, P);
     tstore_vec(xo, N, i, x);
     if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
     if (i > j0) {
@@ -1787,7 +1825,9 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
         Step<T, N, NY, NW> st;
         const typename Cursor<TS, T, M>::Raw rc = q.r;
         cur.terms(p, i, rc, st);
-        prepend_step(st, rc.y, s);
+        T y[NY];
+        rc.meas(y);
+        prepend_step(st, y, s);
       }
     }
     refill(i - 3, q);
