@@ -42,8 +42,9 @@
  *    and the buffer holds ceil(n_states / 1024) * C * 1024 elements (the
  *    caller allocates the padding; padded entries are never read as data and
  *    may be written).  The kernels give each lane `chunk` consecutive states
- *    (a schedule: 4, 8 or 16, see map_problem.chunk), so every access of a
- *    wavefront covers whole cache lines.  Measurements y and per-step lengths
+ *    (a schedule: 4, 8, 16 or 32, see map_problem.chunk); up to 16, every
+ *    access of a wavefront covers whole cache lines (at 32, every other value
+ *    of a row, the rest 16 states later).  Measurements y and per-step lengths
  *    dt are given per state too:
  *    the value of the step that ends at state i (entries at a segment's first
  *    state are ignored).
@@ -141,10 +142,12 @@ typedef struct {
    * step k at base + k * stride (stride 0: one matrix for all steps). */
   const void *F, *c, *L, *W, *H, *r, *R;
   int64_t F_stride, c_stride, L_stride, W_stride, H_stride, r_stride, R_stride;
-  /* Schedule: states per lane (4, 8 or 16), or 0 to let the library choose:
-   * the choice map_autotune recorded for this problem's shape, else the
-   * largest chunk that still gives every second SIMD of the device a
-   * wavefront.
+  /* Schedule: states per lane (4, 8, 16 or 32), or 0 to let the library
+   * choose: the choice map_autotune recorded for this problem's shape, else
+   * 32 when the filter pass then still gives every SIMD of the device four
+   * wavefronts, else the largest of 16, 8 and 4 that gives every second SIMD
+   * a wavefront.  At 32 the filter up-sweep runs 32 states per lane and the
+   * passes after it 16.
    * Results do not depend on it beyond rounding. */
   int32_t chunk;
 } map_problem;
@@ -266,7 +269,7 @@ map_status map_lti_exact_terms(int32_t nx, int32_t nw, const double* F, const do
                                const double* L, const double* W, double dt, double* F_out,
                                double* c_out, double* L_out);
 
-/* The schedule (states per lane: 4, 8 or 16) the scan entry points use for
+/* The schedule (states per lane: 4, 8, 16 or 32) the scan entry points use for
  * this problem: p->chunk if set, else the choice map_autotune recorded for
  * its shape, else the library's heuristic.  Host-only; launches nothing. */
 map_status map_schedule(const map_problem* p, int32_t* chunk_out);

@@ -107,7 +107,7 @@ class Problem:
     dtype     storage precision of every array (torch.float64 or torch.float32)
     arith     arithmetic precision: "f64" (default; with float32 storage this is
               the accurate FP32 mode) or "f32" (float32 storage only)
-    chunk     schedule: states per lane (4, 8, 16) or 0 for the library's choice
+    chunk     schedule: states per lane (4, 8, 16, 32) or 0 for the library's choice
               (an autotuned one for this shape if `autotune` ran, else a
               heuristic)
     """

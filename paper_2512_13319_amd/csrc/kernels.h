@@ -421,8 +421,13 @@ struct Ws {
   T* slane_pre;            // lane-tiled [AffSz] per lane: trajectory map from after the lane's chunk to tile end
   T* stile_agg;            // [AffSz][n_tiles]
   T* stile_carry;          // [N + Sym][n_tiles]  (x, P) after each tile
+  T* lane_half;            // split schedule: lane-tiled [ElemSz] per filter up-sweep lane, fold of its first half
   int64_t n_lanes, n_tiles;
   int64_t chunk;           // states per lane
+  // the filter up-sweep's decomposition (the same unless the schedule is
+  // split, see later_chunk): its lane g1 holds the start of lane g >> k1_shift
+  int64_t n_lanes1, n_tiles1, chunk1;
+  int k1_shift;
 };
 
 // Per-segment accumulators (double): loglik [n_seg], obj [n_seg],
@@ -1034,29 +1039,37 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
     typename Cursor<TS, T, M>::Raw rn;
     cur.fetch(p, j0, rn);
     drain_vmem();
-    for (int64_t i = j0; i < j1; ++i) {
-      const typename Cursor<TS, T, M>::Raw rc = rn;
-      // one state ahead, always issued (a repeat of state i on the last one):
-      // the same number of loads on every path keeps the compiler's waits
-      // for them exact
-      cur.fetch(p, i + 1 < j1 ? i + 1 : i, rn);
-      if (cur.is_head(i)) {
-        T m0[N], P0i[N][N];
-        cur.prior(p, agg.J, agg.eta, m0, P0i);
-        mzero(agg.A);
-        mzero(agg.C);
+    // split schedule: the fold of the first half of the chunk is stored too
+    // (the passes after this one start a lane there)
+    const int64_t jm = ws.lane_half ? min<int64_t>(j0 + (ws.chunk >> 1), j1) : j1;
+    int64_t i = j0;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t je = h == 0 ? jm : j1;
+      for (; i < je; ++i) {
+        const typename Cursor<TS, T, M>::Raw rc = rn;
+        // one state ahead, always issued (a repeat of state i on the last
+        // one): the same number of loads on every path keeps the compiler's
+        // waits for them exact
+        cur.fetch(p, i + 1 < j1 ? i + 1 : i, rn);
+        if (cur.is_head(i)) {
+          T m0[N], P0i[N][N];
+          cur.prior(p, agg.J, agg.eta, m0, P0i);
+          mzero(agg.A);
+          mzero(agg.C);
 #pragma unroll
-        for (int r = 0; r < N; ++r) agg.b[r] = T(0);
-      } else {
-        Step<T, N, M::NY, M::NW> st;
-        cur.terms(p, i, rc, st);
-        T y[M::NY];
-        rc.meas(y);
-        Fresh<T, N, M::NW> f;
-        fresh_from_step(st, y, f);
-        fold_fresh(agg, f);
+          for (int r = 0; r < N; ++r) agg.b[r] = T(0);
+        } else {
+          Step<T, N, M::NY, M::NW> st;
+          cur.terms(p, i, rc, st);
+          T y[M::NY];
+          rc.meas(y);
+          Fresh<T, N, M::NW> f;
+          fresh_from_step(st, y, f);
+          fold_fresh(agg, f);
+        }
+        if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
       }
-      if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
+      if (h == 0 && jm < j1) lt_store_elem(ws.lane_half, g, agg);
     }
   }
   // in-tile inclusive scan
@@ -1188,16 +1201,23 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   if constexpr (kFilter) {
     if (tile < ws.n_tiles) {
       // block carry, then the tile's prefix inside its block, then the lane's
-      const int64_t nb = (ws.n_tiles + 3) >> 2;
-      load_sym(ws.tile_carry, nb, tile >> 2, S, 0);
-      load_vec(ws.tile_carry, nb, tile >> 2, v, Sym<N>::n);
+      // (all in the filter up-sweep's decomposition), then, for the second
+      // half of a split lane, the fold of its first half
+      const int64_t g1 = g >> ws.k1_shift, tile1 = g1 >> 6;
+      const int64_t nb = (ws.n_tiles1 + 3) >> 2;
+      load_sym(ws.tile_carry, nb, tile1 >> 2, S, 0);
+      load_vec(ws.tile_carry, nb, tile1 >> 2, v, Sym<N>::n);
       Elem<T, N> lp;
-      if (tile & 3) {
-        load_elem(ws.tile_pre, ws.n_tiles, tile, lp);
+      if (tile1 & 3) {
+        load_elem(ws.tile_pre, ws.n_tiles1, tile1, lp);
         carry_apply(S, v, lp);
       }
-      lt_load_elem(ws.lane_pre, g, lp);
+      lt_load_elem(ws.lane_pre, g1, lp);
       carry_apply(S, v, lp);
+      if (ws.k1_shift && (g & 1) && j0 < j1) {
+        lt_load_elem(ws.lane_half, g1, lp);
+        carry_apply(S, v, lp);
+      }
     }
   }
   Aff<T, N> sagg;

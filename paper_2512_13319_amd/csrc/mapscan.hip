@@ -130,7 +130,7 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
   if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_CT)
     return fail(MAP_E_ARG, "unknown model %d", p.model);
   if (p.chunk != 0 && !valid_chunk(p.chunk))
-    return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8 or 16", p.chunk);
+    return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8, 16 or 32", p.chunk);
   const int nth = model_ntheta(p);
   if (nth < 0)
     return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
@@ -177,13 +177,17 @@ size_t compute_bytes(int dtype) { return dtype == MAP_F32_FAST ? 4 : 8; }
 size_t storage_bytes(int dtype) { return dtype == MAP_F64 ? 8 : 4; }
 
 // ---------------------------------------------------------------- schedules
-// The schedule is the number of states per lane (4, 8 or 16).  Choices made
-// by map_autotune are kept per problem shape (model, dimensions, dtype, and
-// the powers of two of the state and segment counts); otherwise the largest
-// chunk that still gives at least one wavefront to every second SIMD (fewer
-// states per lane shorten each lane's chain but add wavefront-scan levels
-// per state: at 2^18 + 1 states, 8 per lane on half the SIMDs measured faster
-// than 4 per lane on all of them).
+// The schedule is the number of states per lane (4, 8, 16 or 32, the last
+// split: see later_chunk).  Choices made by map_autotune are kept per problem
+// shape (model, dimensions, dtype, and the powers of two of the state and
+// segment counts).  Otherwise: 32 when its filter up-sweep still gives every
+// SIMD at least four wavefronts in turn (there the up-sweep's fixed cost per
+// wavefront dominates: 4096 ragged segments, 1.6e7 steps, measured 1.96 ->
+// 1.66 ms per fused step), else the largest of 16, 8 and 4 that gives at
+// least one wavefront to every second SIMD (fewer states per lane shorten
+// each lane's chain but add wavefront-scan levels per state: at 2^18 + 1
+// states, 8 per lane on half the SIMDs measured faster than 4 per lane on all
+// of them).
 namespace sched {
 static std::mutex g_mu;
 static std::map<std::string, int> g_tuned;
@@ -211,10 +215,11 @@ int simds() {
 
 int heuristic(const map_problem& p) {
   const int64_t ns = p.n_steps + p.n_seg;
+  if (work_tiles(ns, 32) >= 4 * int64_t(simds())) return 32;
   const int64_t want = simds() / 2;
-  for (int c : kChunks)
+  for (int c : {16, 8})
     if (work_tiles(ns, c) >= want) return c;
-  return kChunks[2];
+  return kMinChunk;
 }
 
 int resolve(const map_problem& p) {
@@ -227,11 +232,17 @@ int resolve(const map_problem& p) {
   return heuristic(p);
 }
 
-// workspace that fits the schedule `resolve` may pick (the smallest chunk when
-// the choice is left to the library)
+// workspace that fits the schedule `resolve` may pick (every schedule when the
+// choice is left to the library)
 size_t ws_bytes_for(const map_problem& p) {
-  const int c = p.chunk != 0 ? p.chunk : kChunks[2];
-  return ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), c).total;
+  const int64_t ns = p.n_steps + p.n_seg;
+  if (p.chunk != 0) return ws_layout(p.nx, ns, compute_bytes(p.dtype), p.chunk).total;
+  size_t m = 0;
+  for (int c : kChunks) {
+    const size_t t = ws_layout(p.nx, ns, compute_bytes(p.dtype), c).total;
+    if (t > m) m = t;
+  }
+  return m;
 }
 }  // namespace sched
 

@@ -10,15 +10,18 @@
 namespace ms {
 
 struct WsLayout {
-  int64_t n_lanes;   // padded to whole tiles
+  int64_t n_lanes;   // padded to whole tiles (passes after the filter up-sweep)
   int64_t n_tiles;
-  size_t off[9];     // counters, lane_pre, tile_agg, tile_carry, slane_pre, stile_agg, stile_carry, tile_pre, stile_suf
+  int64_t n_lanes1;  // the same for the filter up-sweep
+  int64_t n_tiles1;
+  size_t off[10];    // counters, lane_pre, tile_agg, tile_carry, slane_pre, stile_agg, stile_carry, tile_pre,
+                     // stile_suf, lane_half
   size_t total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Work tiles: 64 lanes of `chunk` states (chunk = 4, 8 or 16), one per
+// Work tiles: 64 lanes of `chunk` states (chunk = 4, 8, 16 or 32), one per
 // wavefront.  A final work tile of at most kMergeStates states is not given a
 // wavefront of its own: the last lane of the tile before it runs those states
 // after its own (a grid of 2^k steps has 2^k + 1 states, and a one-state tile
@@ -26,8 +29,14 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // left its compute unit).  The storage layout of state-indexed arrays does
 // not depend on this.
 constexpr int64_t kMergeStates = 8;
-constexpr int kChunks[3] = {16, 8, 4};  // schedules, largest first
-inline bool valid_chunk(int c) { return c == 4 || c == 8 || c == 16; }
+constexpr int kChunks[4] = {32, 16, 8, 4};  // schedules, largest first
+constexpr int kMinChunk = 4;
+inline bool valid_chunk(int c) { return c == 4 || c == 8 || c == 16 || c == 32; }
+// Schedule 32 is split: the filter up-sweep folds 32 states per lane (its
+// wavefront scan, block tree and arrival then cost half as much per state)
+// and also keeps the fold of each lane's first 16; the passes after it run 16
+// per lane, which keeps their streamed accesses on whole cache lines.
+inline int later_chunk(int chunk) { return chunk == 32 ? 16 : chunk; }
 
 inline int64_t work_tiles(int64_t n_states, int64_t chunk) {
   const int64_t ts = 64 * chunk;
@@ -38,8 +47,10 @@ inline int64_t work_tiles(int64_t n_states, int64_t chunk) {
 
 inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   WsLayout w;
-  w.n_tiles = work_tiles(n_states, chunk);
+  w.n_tiles = work_tiles(n_states, later_chunk(int(chunk)));
   w.n_lanes = w.n_tiles * 64;
+  w.n_tiles1 = work_tiles(n_states, chunk);  // <= n_tiles
+  w.n_lanes1 = w.n_tiles1 * 64;
   const int64_t sym = nx * (nx + 1) / 2;
   const int64_t elem = nx * nx + 2 * nx + 2 * sym;
   const int64_t aff = nx * nx + nx + sym;
@@ -47,7 +58,7 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   // flagged backward-filter runs (two-filter form)
   const int64_t rlane = aff > elem + 1 ? aff : elem + 1;
   const int64_t rcarry = nx + sym > elem ? nx + sym : elem;
-  const size_t sizes[9] = {size_t(kCounterWords) * 4,
+  const size_t sizes[10] = {size_t(kCounterWords) * 4,
                            size_t(elem * w.n_lanes) * sz,
                            size_t(elem * w.n_tiles) * sz,
                            size_t((sym + nx) * w.n_tiles) * sz,
@@ -55,9 +66,10 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
                            size_t(rlane * w.n_tiles) * sz,
                            size_t(rcarry * w.n_tiles) * sz,
                            size_t(elem * w.n_tiles) * sz,
-                           size_t(rlane * w.n_tiles) * sz};
+                           size_t(rlane * w.n_tiles) * sz,
+                           chunk == 32 ? size_t(elem * w.n_lanes1) * sz : size_t(0)};
   size_t o = 0;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 10; ++i) {
     w.off[i] = o;
     o += align256(sizes[i]);
   }
@@ -78,7 +90,7 @@ struct SmoothArgs {
   double* g_obj;
   void* ws;
   hipStream_t stream;
-  int chunk;  // states per lane (4, 8 or 16)
+  int chunk;  // states per lane (4, 8, 16 or 32)
 };
 
 // Profiling hook: kernel kinds timed by HIP events when enabled.

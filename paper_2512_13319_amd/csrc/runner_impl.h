@@ -53,10 +53,25 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk) {
   w.stile_carry = reinterpret_cast<T*>(b + l.off[6]);
   w.tile_pre = reinterpret_cast<T*>(b + l.off[7]);
   w.stile_suf = reinterpret_cast<T*>(b + l.off[8]);
+  w.lane_half = chunk == 32 ? reinterpret_cast<T*>(b + l.off[9]) : nullptr;
   w.n_lanes = l.n_lanes;
   w.n_tiles = l.n_tiles;
-  w.chunk = chunk;
+  w.chunk = later_chunk(chunk);
+  w.n_lanes1 = l.n_lanes1;
+  w.n_tiles1 = l.n_tiles1;
+  w.chunk1 = chunk;
+  w.k1_shift = chunk == 32 ? 1 : 0;
   return w;
+}
+
+// The workspace as the filter up-sweep sees it: its own decomposition.
+template <typename T>
+inline Ws<T> up_view(const Ws<T>& w) {
+  Ws<T> u = w;
+  u.n_lanes = w.n_lanes1;
+  u.n_tiles = w.n_tiles1;
+  u.chunk = w.chunk1;
+  return u;
 }
 
 inline unsigned grid_for(int64_t n_tiles) { return unsigned((n_tiles + 3) / 4); }
@@ -138,7 +153,8 @@ hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
+  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
+      p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
@@ -174,8 +190,8 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(
-      p, w, Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
+  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
+      p, up_view(w), Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
@@ -196,7 +212,8 @@ hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& 
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<g, kBlock, 0, a.stream>>>(p, w, Acc{a.loglik, nullptr, nullptr, nullptr});
+  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
+      p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};

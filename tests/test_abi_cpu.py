@@ -211,18 +211,18 @@ def test_nonlinear_model_needs_xbar():
 
 def test_schedule_query():
     """map_schedule: the problem's own chunk when set; otherwise the library's
-    choice, which is always one of the three schedules."""
+    heuristic, one of the four schedules."""
     lib = _lib.load()
     out = ctypes.c_int32(0)
     big = np.array([0, 5000, 12000], dtype=np.int64)
-    for c in (4, 8, 16):
+    for c in (4, 8, 16, 32):
         p = good(big)
         p.chunk = c
         assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == 0
         assert out.value == c
     p = good(big)
     assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == 0
-    assert out.value in (4, 8, 16)
+    assert out.value in (4, 8, 16, 32)
     assert lib.map_schedule(ctypes.byref(p), None) == -1
     p.chunk = 3
     assert lib.map_schedule(ctypes.byref(p), ctypes.byref(out)) == -1

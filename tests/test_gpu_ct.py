@@ -52,7 +52,7 @@ def test_ct_iterated_parity(case, dtype):
     _compare(ms, wl, r, o, TOL[dtype], f"ct {case} {dtype}")
 
 
-@pytest.mark.parametrize("chunk", [8, 16])
+@pytest.mark.parametrize("chunk", [8, 16, 32])
 def test_ct_iterated_parity_schedules(chunk):
     wl = CASES["ct_three"]()
     o = cref.iterate(wl)

@@ -85,10 +85,10 @@ def test_linear_smoother_parity(case, dtype):
     _check_linear(case, dtype, 0)
 
 
-@pytest.mark.parametrize("chunk", [8, 16])
+@pytest.mark.parametrize("chunk", [8, 16, 32])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_linear_smoother_parity_schedules(case, chunk):
-    """The other work decompositions (8 and 16 states per lane)."""
+    """The other work decompositions (8, 16 and 32 states per lane)."""
     _check_linear(case, "f64", chunk)
 
 
@@ -211,20 +211,20 @@ def test_gradients_match_oracle_autograd(model):
 
 
 def test_schedules_agree_with_gradients():
-    """Fused step with the adjoint at 4, 8 and 16 states per lane: every output
-    agrees across schedules and with the oracle."""
+    """Fused step with the adjoint at 4, 8, 16 and 32 states per lane: every
+    output agrees across schedules and with the oracle."""
     ms = _mapscan()
     wl = workloads.cv_batched(n_seg=11, lmin=5.0, lmax=11.5, seed=21)
     o = cref.smooth(wl)
     res = {}
-    for c in (4, 8, 16):
+    for c in (4, 8, 16, 32):
         p = ms.problem_from_workload(wl, dtype=torch.float64, chunk=c)
         r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
         torch.cuda.synchronize()
         res[c] = {k: v.double().cpu().numpy() for k, v in r.items() if v is not None}
         assert rel_err(planes_T(r["xs"]), o["xs"]) <= 1e-9
         assert np.abs(res[c]["loglik"] - o["loglik"]).max() <= 1e-9 * np.abs(o["loglik"]).max()
-    for c in (8, 16):
+    for c in (8, 16, 32):
         for k in ("xs", "Ps", "loglik", "obj", "g_loglik", "g_obj"):
             a, b = res[c][k], res[4][k]
             assert np.abs(a - b).max() <= 1e-10 * max(np.abs(b).max(), 1e-300), (c, k)
@@ -236,7 +236,7 @@ def test_autotune_records_and_reuses_schedule(tmp_path):
     p = ms.problem_from_workload(wl, dtype=torch.float64)
     cache = tmp_path / "schedules.txt"
     c = ms.autotune(p, cache_path=str(cache))
-    assert c in (4, 8, 16)
+    assert c in (4, 8, 16, 32)
     lines = cache.read_text().split("\n")
     key, chosen, ms_ = lines[0].split()
     assert int(chosen) == c and float(ms_) > 0

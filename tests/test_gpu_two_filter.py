@@ -55,7 +55,7 @@ def test_two_filter_parity(case, dtype):
     _check(case, dtype, 0)
 
 
-@pytest.mark.parametrize("chunk", [8, 16])
+@pytest.mark.parametrize("chunk", [8, 16, 32])
 @pytest.mark.parametrize("case", ["batched_tail_heads", "cv_tail8_merged", "linear_tv",
                                   "lorenz_fixed_xbar", "batched_many_blocks"])
 def test_two_filter_parity_schedules(case, chunk):
