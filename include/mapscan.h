@@ -66,8 +66,9 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 4
+#define MAPSCAN_ABI_VERSION 5
 #define MAPSCAN_TILE 1024
+#define MAP_CHECK_FINITE 1
 
 typedef enum {
   MAP_OK = 0,
@@ -75,7 +76,7 @@ typedef enum {
   MAP_E_DIM = -2,         /* dimensions out of range or inconsistent */
   MAP_E_DTYPE = -3,       /* unknown dtype */
   MAP_E_LAYOUT = -4,      /* segment offsets not monotone / inconsistent */
-  MAP_E_NUMERIC = -5,     /* reserved: non-finite result detected */
+  MAP_E_NUMERIC = -5,     /* with MAP_CHECK_FINITE: a non-finite value in the results */
   MAP_E_HIP = -6,         /* a HIP runtime call or kernel launch failed */
   MAP_E_WORKSPACE = -7,   /* workspace missing or too small */
   MAP_E_UNSUPPORTED = -8  /* model/dimension combination not built */
@@ -150,6 +151,13 @@ typedef struct {
    * passes after it 16.
    * Results do not depend on it beyond rounding. */
   int32_t chunk;
+  /* MAP_CHECK_FINITE: the kernels flag any non-finite value they write (S, v,
+   * x*, P^s diagonals, log-likelihood, objective, gradients); the entry point
+   * then waits for its stream, and returns MAP_E_NUMERIC if one was seen (a
+   * non-finite input, or a covariance that is not positive definite).  The
+   * flag lives in the workspace, which the entry point leaves clear again.
+   * Costs one stream synchronisation per call; without it nothing is checked. */
+  int32_t flags;
 } map_problem;
 
 /* Size in bytes of the workspace every scan entry needs for this problem

@@ -110,12 +110,16 @@ class Problem:
     chunk     schedule: states per lane (4, 8, 16, 32) or 0 for the library's choice
               (an autotuned one for this shape if `autotune` ran, else a
               heuristic)
+    check_finite  every call waits for its stream and raises if a non-finite
+              value was written (non-finite inputs, or a covariance that is not
+              positive definite)
     """
 
     def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
-                 dtype=torch.float64, device="cuda", arith="f64", chunk=0):
+                 dtype=torch.float64, device="cuda", arith="f64", chunk=0, check_finite=False):
         _lib.load()
         self.chunk = int(chunk)
+        self.check_finite = bool(check_finite)
         self.model, self.nx, self.ny, self.nw = model, nx, ny, nw
         self.dtype, self.device = dtype, torch.device(device)
         if arith not in ("f64", "f32") or (arith == "f32" and dtype != torch.float32):
@@ -167,6 +171,7 @@ class Problem:
         s.n_theta = self.n_theta
         s.n_seg, s.n_steps = self.n_seg, self.n_steps
         s.chunk = self.chunk
+        s.flags = _lib.MAP_CHECK_FINITE if self.check_finite else 0
         s.seg_off = self.seg_off.data_ptr()
         s.seg_off_host = self.seg_off_host.ctypes.data
         s.dt = self.dt.data_ptr()
@@ -233,12 +238,12 @@ def _nat(p, r, natural):
 
 
 def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, arith="f64",
-                          chunk=0):
+                          chunk=0, check_finite=False):
     """Device-resident Problem from a `workloads.Workload`-like object."""
     return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
                    theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
                    lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith,
-                   chunk=chunk)
+                   chunk=chunk, check_finite=check_finite)
 
 
 def autotune(p: Problem, cache_path=None) -> int:

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libmapscan.so")
 
 MAP_F32, MAP_F64, MAP_F32_FAST = 0, 1, 2
+MAP_CHECK_FINITE = 1
 MODELS = {"linear": 0, "cv": 1, "vdp": 2, "lorenz63": 3, "ct": 4}
 STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: "MAP_E_LAYOUT",
           -5: "MAP_E_NUMERIC", -6: "MAP_E_HIP", -7: "MAP_E_WORKSPACE", -8: "MAP_E_UNSUPPORTED"}
@@ -41,6 +42,7 @@ class MapProblem(ctypes.Structure):
         ("W_stride", ctypes.c_int64), ("H_stride", ctypes.c_int64), ("r_stride", ctypes.c_int64),
         ("R_stride", ctypes.c_int64),
         ("chunk", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 

@@ -12,6 +12,8 @@ constexpr int kArriveWords = kArriveGroups + 1;
 constexpr int kArriveStride = 32;  // words
 // word offsets of the two counter sets (forward and reverse scans)
 constexpr int kCountersFilter = 0, kCountersTraj = kArriveWords * kArriveStride;
-constexpr int kCounterWords = 2 * kArriveWords * kArriveStride;
+// the numeric status word (MAP_CHECK_FINITE) on a line of its own after them
+constexpr int kStatusWord = 2 * kArriveWords * kArriveStride;
+constexpr int kCounterWords = kStatusWord + kArriveStride;
 
 }  // namespace ms

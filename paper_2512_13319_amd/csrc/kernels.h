@@ -428,7 +428,42 @@ struct Ws {
   // split, see later_chunk): its lane g1 holds the start of lane g >> k1_shift
   int64_t n_lanes1, n_tiles1, chunk1;
   int k1_shift;
+  unsigned int* status;    // MAP_CHECK_FINITE: set to 1 when a non-finite value is written; else null
 };
+
+// Non-finite test on the bits.  The library is built with -ffinite-math-only,
+// under which a floating-point test (and the same exponent test on the bits,
+// which the compiler recognises) may be folded to false; the empty asm hides
+// where the bits came from.
+MS_DEVONLY bool nonfinite(double x) {
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  asm volatile("" : "+v"(u));
+  return (u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+}
+MS_DEVONLY bool nonfinite(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  asm volatile("" : "+v"(u));
+  return (u & 0x7f800000u) == 0x7f800000u;
+}
+// a vector and the diagonal of a matrix (a non-finite entry anywhere in a
+// state's moments reaches these within a step)
+template <typename T, int N>
+MS_DEVONLY bool nonfinite_vd(const T (&v)[N], const T (&m)[N][N]) {
+  bool b = false;
+#pragma unroll
+  for (int r = 0; r < N; ++r) b = b | nonfinite(v[r]) | nonfinite(m[r][r]);
+  return b;
+}
+template <typename T, int N>
+MS_DEVONLY bool nonfinite_v(const T (&v)[N]) {
+  bool b = false;
+#pragma unroll
+  for (int r = 0; r < N; ++r) b = b | nonfinite(v[r]);
+  return b;
+}
+MS_DEVONLY void report_nonfinite(unsigned int* status, bool bad) {
+  if (status != nullptr && bad) atomicOr(status, 1u);
+}
 
 // Per-segment accumulators (double): loglik [n_seg], obj [n_seg],
 // g_loglik [n_seg][NTH], g_obj [n_seg][NTH].
@@ -1228,6 +1263,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   T pf = T(0);
   if constexpr (kSuf) elem_identity(pagg);
   double ll = 0.0;
+  bool bad = false;  // a non-finite S, v (MAP_CHECK_FINITE)
   int64_t seg_acc = -1;
   if (j0 < j1) {
     Cursor<TS, T, M> cur;
@@ -1297,6 +1333,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         }
         tstore_sym<TS, T, N, kTraj || kSuf>(So, Sym<N>::n, i, S);
         tstore_vec<TS, T, N, kTraj || kSuf>(vo, N, i, v);
+        if (ws.status) bad = bad | nonfinite_vd(v, S);
         if (kMode == kModeFilter && mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
@@ -1356,6 +1393,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
     }
   }
   if constexpr (kFilter) {
+    if (ws.status) report_nonfinite(ws.status, bad | nonfinite(ll));
     if (fo.want_loglik) {
       double* d[1] = {acc.loglik};
       const int64_t sd[1] = {1};
@@ -1547,6 +1585,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     dstr[1 + t] = dstr[1 + NTH + t] = NTH;
   }
   int64_t seg_acc = -1;
+  bool bad = false;  // a non-finite x*, P^s (MAP_CHECK_FINITE)
   const int64_t j1 = lane_end(g, ws.n_lanes, ns, ws.chunk);
   if (j0 < j1) {
     const int64_t il = j1 - 1;
@@ -1734,6 +1773,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       }
       tstore_vec(xo, N, i, x);
       if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
+      if (ws.status) bad = bad | (kCov ? nonfinite_vd(x, P) : nonfinite_v(x));
       if (cur.is_head(i)) {
         if (to.want_obj) {
           T S0[N][N], v0[N], m0[N], P0i[N][N];
@@ -1767,6 +1807,11 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       body(i, q0);
       q0 = q1;
     }
+  }
+  if (ws.status) {
+#pragma unroll
+    for (int t = 0; t < KV; ++t) bad = bad | nonfinite(val[t]);
+    report_nonfinite(ws.status, bad);
   }
   if (to.want_obj || kGrad) flush_block<KV>(seg_acc, val, dst, dstr);
 }
@@ -1828,6 +1873,7 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
   refill(il, q0);
   refill(il - 1, q1);
   refill(il - 2, q2);
+  bool bad = false;  // a non-finite x*, P^s (MAP_CHECK_FINITE)
   auto body = [&](int64_t i, Ahead& q) {
     T x[N], P[N][N];
     T S[N][N], v[N];
@@ -1836,6 +1882,7 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
     two_filter_point<T, N, kCov>(S, v, s, x, P);
     tstore_vec(xo, N, i, x);
     if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
+    if (ws.status) bad = bad | (kCov ? nonfinite_vd(x, P) : nonfinite_v(x));
     if (i > j0) {
       if (cur.is_head(i)) {
         // state i - 1 ends the previous segment: nothing comes after it
@@ -1863,6 +1910,7 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
     body(i, q0);
     q0 = q1;
   }
+  report_nonfinite(ws.status, bad);
 }
 
 // --------------------------------------------------------------------------- misc

@@ -131,6 +131,7 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
     return fail(MAP_E_ARG, "unknown model %d", p.model);
   if (p.chunk != 0 && !valid_chunk(p.chunk))
     return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8, 16 or 32", p.chunk);
+  if (p.flags & ~MAP_CHECK_FINITE) return fail(MAP_E_ARG, "unknown flags 0x%x", unsigned(p.flags));
   const int nth = model_ntheta(p);
   if (nth < 0)
     return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
@@ -246,6 +247,26 @@ size_t ws_bytes_for(const map_problem& p) {
 }
 }  // namespace sched
 
+// MAP_CHECK_FINITE: the kernels set the workspace's status word when they
+// write a non-finite value.  After a successful launch sequence it is read
+// back (one stream synchronisation), and cleared again when set.
+map_status finish_check(const map_problem& p, void* ws, hipStream_t st, map_status s) {
+  if (s != MAP_OK || !(p.flags & MAP_CHECK_FINITE)) return s;
+  unsigned int* w = static_cast<unsigned int*>(ws) + kStatusWord;
+  unsigned int word = 0;
+  s = hip_status(hipMemcpyAsync(&word, w, sizeof(word), hipMemcpyDeviceToHost, st), "status read");
+  if (s == MAP_OK) s = hip_status(hipStreamSynchronize(st), "status read");
+  if (s != MAP_OK) return s;
+  if (word != 0) {
+    k_clear_words<<<1, 64, 0, st>>>(w, 1);
+    s = hip_status(hipGetLastError(), "status clear");
+    if (s != MAP_OK) return s;
+    return fail(MAP_E_NUMERIC, "non-finite value in the results (non-finite inputs, or a "
+                               "covariance that is not positive definite)");
+  }
+  return MAP_OK;
+}
+
 map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
   const size_t need =
       ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), sched::resolve(p)).total;
@@ -337,7 +358,7 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return dispatch(*p, DoFilter{*p, a});
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoFilter{*p, a}));
 }
 
 map_status map_smoother_scan(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
@@ -348,7 +369,7 @@ map_status map_smoother_scan(const map_problem* p, const void* S, const void* v,
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
                nullptr, nullptr, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return dispatch(*p, DoSmoother{*p, a, false});
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoSmoother{*p, a, false}));
 }
 
 map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps, double* loglik,
@@ -362,7 +383,7 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return dispatch(*p, DoSmooth{*p, a});
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoSmooth{*p, a}));
 }
 
 map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps,
@@ -373,7 +394,7 @@ map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* x
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return dispatch(*p, DoTwoFilter{*p, a});
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoTwoFilter{*p, a}));
 }
 
 map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const void* xbar0,
@@ -416,7 +437,7 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
     if (s != MAP_OK) return s;
     cur = 1 - cur;
   }
-  return MAP_OK;
+  return finish_check(*p, ws, st, MAP_OK);
 }
 
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
@@ -430,7 +451,7 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
                g_loglik, g_obj, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return dispatch(*p, DoSmoother{*p, a, true});
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoSmoother{*p, a, true}));
 }
 
 map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,
@@ -439,6 +460,7 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
   if (s != MAP_OK) return s;
   if (chunk_out == nullptr) return fail(MAP_E_ARG, "chunk_out is NULL");
   map_problem q = *p;
+  q.flags &= ~MAP_CHECK_FINITE;  // timing runs check nothing
   q.chunk = 0;
   if (ws == nullptr || ws_bytes < sched::ws_bytes_for(q))
     return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,

@@ -40,7 +40,7 @@ inline Prob<T> make_prob(const map_problem& q) {
 }
 
 template <typename T>
-inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk) {
+inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk, int flags) {
   WsLayout l = ws_layout(nx, n_states, sizeof(T), chunk);
   char* b = static_cast<char*>(base);
   Ws<T> w;
@@ -61,6 +61,7 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk) {
   w.n_tiles1 = l.n_tiles1;
   w.chunk1 = chunk;
   w.k1_shift = chunk == 32 ? 1 : 0;
+  w.status = (flags & MAP_CHECK_FINITE) ? w.counters + kStatusWord : nullptr;
   return w;
 }
 
@@ -150,7 +151,7 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
   k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
@@ -168,7 +169,7 @@ hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a, bool grad) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const int64_t nth = M::NTH;
   MS_CHECK(zero(Acc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
                 q.n_seg, nth, a.stream));
@@ -186,7 +187,7 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
@@ -209,7 +210,7 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& a) {
   Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk);
+  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
   k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(

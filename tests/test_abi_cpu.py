@@ -104,6 +104,20 @@ def test_workspace_bytes_by_schedule(seg):
                                None) == -1
 
 
+def test_flags_are_validated(seg):
+    """Only MAP_CHECK_FINITE is a known flag; other bits are rejected before any
+    launch."""
+    lib = _lib.load()
+    p = good(seg)
+    p.flags = 2
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+    assert b"flags" in lib.map_last_error()
+    p.flags = _lib.MAP_CHECK_FINITE
+    assert lib.map_workspace_bytes(ctypes.byref(p)) > 0
+    assert "#define MAP_CHECK_FINITE %d" % _lib.MAP_CHECK_FINITE in open(HEADER).read()
+
+
 def test_autotune_validates_before_running(seg):
     lib = _lib.load()
     out = ctypes.c_int32(0)
