@@ -157,7 +157,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures a single GPU: this build runs the scan on one MI355X "
+        print("bench.py measures a single GPU: the library runs each scan on one MI355X "
               "(multi-GPU sharding is a design note only); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
