@@ -128,14 +128,17 @@ def _check_linear(case, dtype, chunk):
     assert e_ll <= tol and e_ob <= tol, msg
 
 
+@pytest.mark.parametrize("case,chunk", [("cv_batched", 0), ("batched_many_blocks", 32)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_filter_moments_and_separate_smoother(dtype):
+def test_filter_moments_and_separate_smoother(dtype, case, chunk):
     """map_filter_scan (with m, P) followed by map_smoother_scan equals the
-    fused map_smooth and the oracle."""
+    fused map_smooth and the oracle; also with the split schedule (filter
+    up-sweep at 32 states per lane over many blocks, the passes after it at
+    16)."""
     ms = _mapscan()
-    wl = CASES["cv_batched"]().rounded(dtype)
+    wl = CASES[case]().rounded(dtype)
     o = cref.smooth(wl)
-    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype], chunk=chunk)
     ft = ms.filter_scan(p, moments=True, loglik=True, natural=False)
     s = ms.smoother_scan(p, ft["S"], ft["v"], covariances=True, objective=True)
     torch.cuda.synchronize()
