@@ -494,7 +494,12 @@ def measure_exact(args, ms, _lib, lib, timed, tdt, s, wl):
     wx = workloads.Workload(name="cv_exact", model="linear", nx=4, ny=2, nw=4, seg_off=wl.seg_off,
                             dt=wl.dt, y=wl.y, theta=np.zeros((1, 0)), m0=wl.m0, P0=wl.P0,
                             x_true=wl.x_true, lin=lin)
-    p = ms.problem_from_workload(wx, dtype=tdt, device="cuda:0")
+    # one step length for all steps: every term of the general linear model is
+    # shared, so the kernels build a step's terms once per block
+    import dataclasses
+    assert np.all(wx.dt == wx.dt[0])
+    p = ms.problem_from_workload(dataclasses.replace(wx, dt=np.asarray(float(wx.dt[0]))),
+                                 dtype=tdt, device="cuda:0")
     if not args.no_autotune:
         ms.autotune(p)
     f64 = torch.float64

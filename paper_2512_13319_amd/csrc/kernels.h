@@ -484,6 +484,7 @@ struct Cursor {
   int64_t head;       // its first state
   int64_t next_head;  // first state of the next segment (n_states after the last)
   T th[NTH_];
+  const T* sstep = nullptr;  // general linear model, every term shared: the step's terms in LDS
 
   MS_DEVONLY void load_seg(const Prob<TS>& p) {
     head = p.seg_off[s] + s;
@@ -562,6 +563,12 @@ struct Cursor {
         st.r[a] = ya - wrap_angle(ya - st.r[a]);
       }
     } else {
+      if (sstep != nullptr) {
+        T* d = reinterpret_cast<T*>(&st);
+#pragma unroll
+        for (int q = 0; q < int(sizeof(st) / sizeof(T)); ++q) d[q] = sstep[q];
+        return;
+      }
       st.dt = dt;
       const TS* F = p.F + k * p.sF;
       const TS* c = p.c + k * p.sc;
@@ -636,6 +643,40 @@ struct Cursor {
     mv(P0i, m0, v0);
   }
 };
+
+// General linear model with every matrix and the step length shared by all
+// steps: every step has the same terms.  One thread of the block builds them
+// into LDS at the start (through the general path), and the cursors read them
+// from there instead of loading 66 values and repeating a Cholesky
+// factorisation, a product and an inverse at every step.  Every thread of the
+// block calls it, before any thread leaves.
+template <typename T, class M>
+struct SharedStep {
+  static constexpr int n =
+      M::NTH == 0 ? int(sizeof(Step<T, M::NX, M::NY, M::NW>) / sizeof(T)) : 1;
+};
+template <typename TS, typename T, class M>
+MS_DEVONLY const T* shared_step(const Prob<TS>& p, T* lds) {
+  if constexpr (M::NTH == 0) {
+    if (p.sF != 0 || p.sc != 0 || p.sL != 0 || p.sW != 0 || p.sH != 0 || p.sr != 0 ||
+        p.sR != 0 || p.dt_stride != 0)
+      return nullptr;
+    if (threadIdx.x == 0) {
+      Cursor<TS, T, M> c;
+      c.s = 0;
+      typename Cursor<TS, T, M>::Raw r;
+      r.dt = p.dt[0];
+      Step<T, M::NX, M::NY, M::NW> st;
+      c.terms(p, 1, r, st);  // step index 0; every index reads the same matrices
+      const T* src = reinterpret_cast<const T*>(&st);
+      for (int q = 0; q < SharedStep<T, M>::n; ++q) lds[q] = src[q];
+    }
+    __syncthreads();
+    return lds;
+  } else {
+    return nullptr;
+  }
+}
 
 // --------------------------------------------------------------------------- reductions
 // Segmented sum over the lanes of a block (segment ids non-decreasing with the
@@ -1060,6 +1101,8 @@ MS_DEVONLY void zero_acc_grid(const Acc& a, int64_t n_seg, int64_t nth) {
 template <typename TS, typename T, class M>
 __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   constexpr int N = M::NX;
+  __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
+  const T* sstep = shared_step<TS, T, M>(p, s_step);
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   zero_acc_grid(zacc, p.n_seg, M::NTH > 0 ? M::NTH : 1);
@@ -1070,6 +1113,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
   elem_identity(agg);
   if (j0 < j1) {
     Cursor<TS, T, M> cur;
+    cur.sstep = sstep;
     cur.init(p, j0);
     typename Cursor<TS, T, M>::Raw rn;
     cur.fetch(p, j0, rn);
@@ -1222,6 +1266,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   constexpr bool kFilter = kMode != kModeTrajOnly;
   constexpr bool kTraj = kMode == kModeFused || kMode == kModeTrajOnly;
   constexpr bool kSuf = kMode == kModeTwoFilter;
+  __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
+  const T* sstep = shared_step<TS, T, M>(p, s_step);
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
@@ -1267,6 +1313,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
   int64_t seg_acc = -1;
   if (j0 < j1) {
     Cursor<TS, T, M> cur;
+    cur.sstep = sstep;
     cur.init(p, j0);
     seg_acc = cur.s;
     typename Cursor<TS, T, M>::Raw rn;
@@ -1548,6 +1595,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
   constexpr int KV = 1 + 2 * NTH;
+  __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
+  const T* sstep = shared_step<TS, T, M>(p, s_step);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
   const int64_t j0 = g * ws.chunk;
@@ -1590,6 +1639,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
   if (j0 < j1) {
     const int64_t il = j1 - 1;
     Cursor<TS, T, M> cur;
+    cur.sstep = sstep;
     cur.init(p, il);
     seg_acc = cur.s;
     // Filter moments of a state and inputs of the state after it, in three
@@ -1825,6 +1875,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
 template <typename TS, typename T, class M, bool kCov>
 __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws, TrajOut to) {
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
+  __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
+  const T* sstep = shared_step<TS, T, M>(p, s_step);
   const int64_t g = logical_block() * kBlock + threadIdx.x;
   const int64_t tile = g >> 6;
   const int64_t j0 = g * ws.chunk;
@@ -1856,6 +1908,7 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
   }
   const int64_t il = j1 - 1;
   Cursor<TS, T, M> cur;
+  cur.sstep = sstep;
   cur.init(p, il);
   // filter moments and step inputs of a state, in three rotating buffers
   // refilled three states ahead (as in the trajectory fix-up)

@@ -52,11 +52,19 @@ def exact_pair(T, dt, gamma, q=0.5, r=0.05, c=(0, 0, 0.15, -0.1), seed=61, dtype
     return wg, wo
 
 
+@pytest.mark.parametrize("shared_dt", [False, True])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("T,gamma", [(3 * 1024 + 77, 0.0), (2055, 0.6)])
-def test_lti_exact_parity(T, gamma, dtype):
+def test_lti_exact_parity(T, gamma, dtype, shared_dt):
+    """shared_dt: one step length for all steps, so that every term of the
+    general linear model is shared (the kernels then build a step's terms once
+    per block); otherwise the same value given per step."""
+    import dataclasses
+
     import paper_2512_13319_amd as ms
     wg, wo = exact_pair(T, 1e-3, gamma, dtype=dtype)
+    if shared_dt:
+        wg = dataclasses.replace(wg, dt=np.asarray(float(wg.dt[0])))
     if dtype == "f32":
         # the FP32 run stores rounded terms; the oracle sees the same rounding
         for k in ("F", "c", "L", "W", "H", "r", "R"):
