@@ -133,8 +133,8 @@ def main():
                     help="storage type of inputs and outputs (arithmetic is FP64 in both)")
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=6144)
-    ap.add_argument("--cpu-sample-ct", type=int, default=16,
+    ap.add_argument("--cpu-sample-steps", type=int, default=8192)
+    ap.add_argument("--cpu-sample-ct", type=int, default=64,
                     help="tracks of the coordinated-turn CPU-baseline sample")
     ap.add_argument("--cpu-sample-tf", type=int, default=2 ** 20,
                     help="steps of the two-filter CPU-baseline sample")
@@ -149,7 +149,7 @@ def main():
                     help="skip the coordinated-turn (iterated nonlinear) measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched ragged-segment measurement (4096 segments)")
-    ap.add_argument("--cpu-sample-segs", type=int, default=256,
+    ap.add_argument("--cpu-sample-segs", type=int, default=1024,
                     help="segments of the batched CPU-baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
