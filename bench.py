@@ -80,22 +80,25 @@ def kernel_bytes(nx, ny, s, kind):
     }[kind]
 
 
-def roofline_for(kern, rec, fresh, n_states, nx, ny, s, dtype):
+def roofline_for(kern, rec, fresh, n_states, nx, ny, s, dtype, schedule=None):
     """Roofline object of the longest kernel in `kern` {name: (count, ms)}.
 
     The bound is the roof the kernel's arithmetic intensity puts it under:
     counted FP64 flops per algorithmic HBM byte against the ridge point
     78.6 TFLOP/s / 8 TB/s (9.8 flop/B). Below the ridge the kernel is priced
     against HBM with its algorithmic bytes, above it against the FP64 vector
-    roof with its counted flops. Without a flop count for this workload it is
-    priced against HBM."""
+    roof with its counted flops. Without a flop count for this workload, or
+    with one taken at another schedule (states per lane: the per-state work of
+    the scans depends on it), it is priced against HBM."""
     dom = max((k for k in kern if k != "aux"), key=lambda k: kern[k][1])
     dom_ms = kern[dom][1]
     bytes_state = kernel_bytes(nx, ny, s, dom)
     bytes_dom = bytes_state * n_states
     hbm_gbs = bytes_dom / (dom_ms * 1e-3) / 1e9
     kc = (rec or {}).get("kernels", {}).get(dom)
-    counted = kc is not None and kc.get("n_states") == n_states
+    rec_sched = (rec or {}).get("states_per_lane")
+    same_sched = schedule is None or rec_sched is None or rec_sched == schedule
+    counted = kc is not None and kc.get("n_states") == n_states and same_sched
     ridge = VALU_PEAK_TFLOPS[dtype] * 1e3 / HBM_PEAK_GBS
     intensity = kc["flops_fp64_per_state"] / bytes_state if counted else None
     if counted and intensity >= ridge:
@@ -116,6 +119,8 @@ def roofline_for(kern, rec, fresh, n_states, nx, ny, s, dtype):
                      "fp64_achieved_TFLOPs": round(kc["flops_fp64_per_state"] * n_states
                                                    / (dom_ms * 1e-3) / 1e12, 3),
                      "counters_current": fresh})
+    if not same_sched:
+        roof["counters_schedule"] = {"profiled": rec_sched, "measured": schedule}
     roof.update({
         "kernel": dom, "kernel_ms": round(dom_ms, 4),
         "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
@@ -145,6 +150,9 @@ def main():
                     help="skip the two-filter smoother measurement")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the exact-discretisation (linear-model path) measurement")
+    ap.add_argument("--ct-chunk", type=int, default=0,
+                    help="states per lane for the coordinated-turn solve (0: autotuned, or the "
+                         "library's heuristic with --no-autotune)")
     ap.add_argument("--no-ct", action="store_true",
                     help="skip the coordinated-turn (iterated nonlinear) measurement")
     ap.add_argument("--no-batched", action="store_true",
@@ -239,7 +247,7 @@ def main():
     step_bytes = (p.ny + 2 * (nsym + p.nx) + p.nx + nsym) * s * p.n_states
     rec, fresh = counter_record(args.dtype)
     # dominant kernel of the fwd+adjoint step
-    roofline = roofline_for(kern_fa, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)
+    roofline = roofline_for(kern_fa, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype, chunk)
     roofline["step_hbm_frac"] = round(step_bytes / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     two_filter = None
@@ -262,7 +270,7 @@ def main():
                       "eager_ms_per_step": round(ms_tf_e, 4),
                       "outputs": "filter S, v; smoothed x*, P^s; log-likelihood",
                       "roofline": roofline_for(kern_tf, rec, fresh, p.n_states, p.nx, p.ny, s,
-                                               args.dtype)}
+                                               args.dtype, chunk)}
 
     res = {
         "metric": METRIC,
@@ -363,8 +371,8 @@ def measure_ct(args, ms, _lib, lib, timed, tdt, s):
     import workloads
 
     wl = workloads.ct()
-    p = ms.problem_from_workload(wl, dtype=tdt, device="cuda:0")
-    if not args.no_autotune:
+    p = ms.problem_from_workload(wl, dtype=tdt, device="cuda:0", chunk=args.ct_chunk)
+    if not args.no_autotune and args.ct_chunk == 0:
         # the autotuner times one linear solve: linearise about the simulated path
         p.set_xbar(torch.as_tensor(wl.x_true))
         ms.autotune(p)
@@ -386,14 +394,15 @@ def measure_ct(args, ms, _lib, lib, timed, tdt, s):
         ms_g, _, _ = timed(g.replay, args.steps, args.warmup, False)
     rec, fresh = counter_record(args.dtype, "ct5_64x2p14")
     # per-launch averages pool the 5 iterations (the last with covariances)
-    roof = roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)
+    roof = roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype, ms.schedule(p))
     res = {"value": wl.n_steps / (ms_g * 1e-3), "unit": "time-steps/s",
            "ms_per_step": ms_g, "eager_ms_per_step": round(ms_e, 4),
            "workload": "coordinated-turn SDE (Sec. 5.2) nx=5 ny=2 (range, bearing), 64 tracks x "
                        "2^14 steps dt=1e-3, 5 Gauss-Newton iterations from m0; x*, P^s, "
                        "log-likelihood, objective of the last",
            "n_iter": wl.n_iter, "n_steps": wl.n_steps,
-           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "schedule": {"states_per_lane": ms.schedule(p),
+                        "autotuned": not args.no_autotune and args.ct_chunk == 0},
            "roofline": roof}
     return res, wl
 
@@ -436,7 +445,8 @@ def measure_batched(args, ms, _lib, lib, timed):
                        "and adjoint d/d(gamma,q,r)" % wl.n_steps,
            "n_seg": int(n), "n_steps": int(wl.n_steps), "storage": "f32",
            "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
-           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, 4, "f32")}
+           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, 4, "f32",
+                                     ms.schedule(p))}
     return res, wl
 
 
@@ -522,7 +532,8 @@ def measure_exact(args, ms, _lib, lib, timed, tdt, s, wl):
                        "(matrix-exponential) dynamics in the elements, general linear model "
                        "nx=4 ny=2 nw=4; x*, P^s, log-likelihood, objective",
            "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
-           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype)}
+           "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype,
+                                     ms.schedule(p))}
     return res, wx
 
 
