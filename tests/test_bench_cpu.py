@@ -46,3 +46,14 @@ def test_stale_or_missing_counters():
     rec["kernels"]["traj_down_adjoint"]["n_states"] = N - 1
     r = bench.roofline_for(kern, rec, True, N, 4, 2, 8, "f64")
     assert r["bound"] == "hbm" and r["traffic"] is None and "flops_per_state" not in r
+
+
+def test_counts_taken_at_another_schedule_are_not_used():
+    kern = {"filter_up": (1, 0.066), "fused_down": (1, 0.06)}
+    rec = _rec("filter_up", 950.0)
+    rec["states_per_lane"] = 16
+    r = bench.roofline_for(kern, rec, True, N, 4, 2, 8, "f64", 16)
+    assert r["bound"] == "alu" and r["traffic"] == 123456789 and "counters_schedule" not in r
+    r = bench.roofline_for(kern, rec, True, N, 4, 2, 8, "f64", 32)
+    assert r["bound"] == "hbm" and r["traffic"] is None
+    assert r["counters_schedule"] == {"profiled": 16, "measured": 32}
