@@ -1,0 +1,5 @@
+// Instantiations: general linear model (nx, ny, nw) = (1, 1, 1).
+#include "runner_impl.h"
+namespace ms {
+MS_INSTANTIATE(ModelLinear<1 MS_COMMA 1 MS_COMMA 1>)
+}  // namespace ms

@@ -1,0 +1,5 @@
+// Instantiations: general linear model (nx, ny, nw) = (3, 2, 3).
+#include "runner_impl.h"
+namespace ms {
+MS_INSTANTIATE(ModelLinear<3 MS_COMMA 2 MS_COMMA 3>)
+}  // namespace ms

@@ -1,6 +1,5 @@
-// Instantiations: nonlinear models (Van der Pol, Lorenz-63).
+// Instantiations: Lorenz-63 model.
 #include "runner_impl.h"
 namespace ms {
-MS_INSTANTIATE(ModelVdP)
 MS_INSTANTIATE(ModelLorenz63)
 }  // namespace ms

@@ -685,3 +685,146 @@ def test_implicit_euler_and_exact_agree_to_first_order():
         diffs.append(np.abs(ex - ie).max())
     q = [a / b for a, b in zip(diffs[:-1], diffs[1:])]
     assert all(1.7 < x < 2.3 for x in q), (diffs, q)
+
+
+# ------------------------------------------------------------------ Lorenz-63 terms
+LORENZ_TH = np.array([10.0, 28.0, 8.0 / 3.0, 0.5, 0.5])
+
+
+def test_lorenz_drift_fixed_points_divergence_and_symmetry():
+    """The oracle's Lorenz-63 drift against properties of the system that do
+    not come from its formula: it vanishes at the origin and at the two
+    equilibria (+-sqrt(beta (rho - 1)), +-sqrt(beta (rho - 1)), rho - 1); its
+    divergence, the trace of F, is the constant -(sigma + 1 + beta) (the
+    divergence term of eq. OM is therefore constant for this model); and it is
+    equivariant under (x1, x2, x3) -> (-x1, -x2, x3)."""
+    sg, rho, be = LORENZ_TH[:3]
+    a = np.sqrt(be * (rho - 1.0))
+    eq = np.array([[0.0, 0.0, 0.0], [a, a, rho - 1.0], [-a, -a, rho - 1.0]])
+    f, h = _models.drift_torch("lorenz63", torch.tensor(LORENZ_TH), torch.tensor(eq), 3)
+    assert np.abs(f.numpy()).max() < 1e-12
+    assert np.abs(h.numpy() - eq).max() == 0.0            # full-state measurement
+    rng = np.random.default_rng(7)
+    x = rng.normal(0, 8, (20, 3))
+    for terms in (_models.terms_numpy, lambda *a: [t.numpy() for t in _models.terms_torch(
+            a[0], torch.tensor(a[1]), torch.tensor(a[2]), a[3])]):
+        F = np.asarray(terms("lorenz63", LORENZ_TH, x, 3)[0])
+        assert np.abs(np.trace(F, axis1=1, axis2=2) + (sg + 1.0 + be)).max() < 1e-12
+    P = np.diag([-1.0, -1.0, 1.0])
+    fx, _ = _models.drift_torch("lorenz63", torch.tensor(LORENZ_TH), torch.tensor(x), 3)
+    fpx, _ = _models.drift_torch("lorenz63", torch.tensor(LORENZ_TH), torch.tensor(x @ P), 3)
+    assert np.abs(fpx.numpy() - fx.numpy() @ P).max() < 1e-12
+    # the equilibria C+- are the only ones with x3 > 0: f(x) = 0 there fixes
+    # x1 = x2 and x1^2 = beta x3, x3 = rho - 1 (a sign slip in any of the
+    # three components moves one of them)
+    assert np.abs(f.numpy()[1:, 2]).max() < 1e-12
+
+
+@pytest.mark.parametrize("impl", ["numpy", "torch"])
+def test_lorenz_taylor_terms_match_finite_differences(impl):
+    """F = df/dx and H = dh/dx at xbar by central differences of the drift
+    and measurement; c and r make the expansion exact at xbar (both the numpy
+    terms, which feed the C oracle, and the torch terms, which give the
+    gradient truth)."""
+    rng = np.random.default_rng(4)
+    xb = rng.normal(0, 8, (12, 3)) + np.array([0.0, 0.0, 20.0])
+    th = LORENZ_TH.copy()
+    if impl == "numpy":
+        F, c, L, W, H, r, R = _models.terms_numpy("lorenz63", th, xb, 3)
+    else:
+        F, c, L, W, H, r, R = (t.numpy() for t in _models.terms_torch(
+            "lorenz63", torch.tensor(th), torch.tensor(xb), 3))
+    tt = torch.tensor(th)
+
+    def fh(x):
+        f, hx = _models.drift_torch("lorenz63", tt, torch.tensor(x), 3)
+        return f.numpy(), hx.numpy()
+    eps = 1e-5
+    for j in range(3):
+        dp = xb.copy(); dp[:, j] += eps
+        dm = xb.copy(); dm[:, j] -= eps
+        (fp, hp), (fm, hm) = fh(dp), fh(dm)
+        # f is quadratic: the central difference is exact up to rounding
+        assert np.abs((fp - fm) / (2 * eps) - F[:, :, j]).max() < 1e-7
+        assert np.abs((hp - hm) / (2 * eps) - H[:, :, j]).max() < 1e-9
+    f0, h0 = fh(xb)
+    assert np.abs(np.einsum("kij,kj->ki", F, xb) + c - f0).max() < 1e-12
+    assert np.abs(np.einsum("kij,kj->ki", H, xb) + r - h0).max() < 1e-12
+    assert np.allclose(L @ W @ L.T, th[3] * np.eye(3)) and np.allclose(R, th[4] * np.eye(3))
+
+
+def test_lorenz_terms_theta_dependence_matches_differences():
+    """The theta dependence of the torch terms (which the oracle's autograd
+    gradients differentiate) against central differences of the drift in
+    theta: d(F xbar + c)/d theta = df/d theta at xbar, and d F / d theta equals
+    the difference of F."""
+    rng = np.random.default_rng(5)
+    xb = torch.tensor(rng.normal(0, 8, (6, 3)))
+    th = torch.tensor(LORENZ_TH).requires_grad_(True)
+    F, c, L, W, H, r, R = _models.terms_torch("lorenz63", th, xb, 3)
+    lin = torch.einsum("kij,kj->ki", F, xb) + c
+    for k in range(6):
+        for i in range(3):
+            g, = torch.autograd.grad(lin[k, i], th, retain_graph=True)
+            for t in range(3):
+                e = 1e-6 * LORENZ_TH[t]
+                tp, tm = LORENZ_TH.copy(), LORENZ_TH.copy()
+                tp[t] += e
+                tm[t] -= e
+                fp, _ = _models.drift_torch("lorenz63", torch.tensor(tp), xb, 3)
+                fm, _ = _models.drift_torch("lorenz63", torch.tensor(tm), xb, 3)
+                fd = (fp[k, i] - fm[k, i]).item() / (2 * e)
+                assert abs(g[t].item() - fd) < 1e-6 * max(1.0, abs(fd)), (k, i, t)
+    for t in range(3):
+        e = 1e-6 * LORENZ_TH[t]
+        tp, tm = LORENZ_TH.copy(), LORENZ_TH.copy()
+        tp[t] += e
+        tm[t] -= e
+        Fp = _models.terms_numpy("lorenz63", tp, xb.numpy(), 3)[0]
+        Fm = _models.terms_numpy("lorenz63", tm, xb.numpy(), 3)[0]
+        dF = np.zeros((3, 3))
+        for a in range(3):
+            for b in range(3):
+                gab, = torch.autograd.grad(F[0, a, b], th, retain_graph=True, allow_unused=True)
+                dF[a, b] = 0.0 if gab is None else gab[t].item()
+        assert np.abs((Fp[0] - Fm[0]) / (2 * e) - dF).max() < 1e-6
+
+
+def test_lorenz_gauss_newton_matches_nonlinear_least_squares():
+    """Gauss--Newton (Sec. 4.4) on Lorenz-63 (Q = q I invertible) converges to
+    the minimiser of the nonlinear discretised objective found by a generic
+    trust-region least-squares solver on its stacked residuals (prior, the
+    step residuals x_k - x_{k-1} - dt f(x_k) weighted by (dt q)^{-1/2}, the
+    measurements weighted by (dt / r)^{1/2}); the objective decreases and is
+    stationary at the last iterate."""
+    wl = workloads.lorenz63(n_seg=1, T=40, dt=0.01, seed=72, n_iter=12)
+    seg = ref.workload_segment(wl, 0)
+    its, out = ref.gauss_newton("lorenz63", seg["theta"], seg["dt"], seg["y"], seg["m0"],
+                                seg["P0"], 3, 12)
+    obj = [ref.map_objective_nonlinear("lorenz63", seg["theta"], x, seg["dt"], seg["y"],
+                                       seg["m0"], seg["P0"], 3).item() for x in its]
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(obj[2:], obj[3:]))
+    q, rr = wl.theta[0][3], wl.theta[0][4]
+    T = wl.n_steps
+    dt = wl.dt[0]
+    y = wl.y.T
+    P0h = np.linalg.cholesky(np.linalg.inv(wl.P0[0])).T
+    tt = torch.tensor(wl.theta[0])
+
+    def resid(z):
+        x = z.reshape(T + 1, 3)
+        f, hx = _models.drift_torch("lorenz63", tt, torch.tensor(x[1:]), 3)
+        D = (x[1:] - x[:-1] - dt * f.numpy()) / np.sqrt(dt * q)
+        E = (y - hx.numpy()) * np.sqrt(dt / rr)
+        return np.concatenate([P0h @ (x[0] - wl.m0[0]), D.reshape(-1), E.reshape(-1)])
+
+    sol = scipy.optimize.least_squares(resid, its[-1].numpy().reshape(-1) + 0.05, xtol=1e-15,
+                                       ftol=1e-15, gtol=1e-15)
+    x_ls = sol.x.reshape(T + 1, 3)
+    assert np.abs(its[-1].numpy() - x_ls).max() < 1e-7 * np.abs(x_ls).max()
+    assert abs(0.5 * np.sum(resid(sol.x) ** 2) - obj[-1]) < 1e-9 * abs(obj[-1])
+    x = its[-1].clone().requires_grad_(True)
+    M = ref.map_objective_nonlinear("lorenz63", seg["theta"], x, seg["dt"], seg["y"],
+                                    seg["m0"], seg["P0"], 3)
+    g, = torch.autograd.grad(M, x)
+    assert g.abs().max().item() < 1e-6
