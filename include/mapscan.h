@@ -182,6 +182,11 @@ map_status map_build_elements(const map_problem* p, void* elems, void* stream);
  * Sec. 4.1; information form of the Kalman--Bucy filter, Sec. 2.5):
  *   S     out tiled [nx(nx+1)/2] per state: information matrix S_k = P_k^{-1}
  *   v     out tiled [nx] per state:         information vector v_k = P_k^{-1} m_k
+ *         with FP64 storage; with FP32 storage (MAP_F32, MAP_F32_FAST) the
+ *         filter mean m_k itself (v rounded to FP32 loses the relative
+ *         precision of small components of m: S^{-1} spreads its rounding
+ *         over every component).  The smoother entry points read the plane
+ *         the same way.
  *   m, P  optional out (NULL to skip) filter mean and covariance
  *   loglik optional out [n_seg] (double): log p(y_1..y_T) by the
  *         prediction-error decomposition of the same discrete model. */

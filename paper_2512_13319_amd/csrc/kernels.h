@@ -208,6 +208,40 @@ MS_DEVONLY void tstore_mat(P* base, int C, int64_t i, const T (&a)[N][M], int c0
     for (int q = 0; q < M; ++q) base[tix(i, c0 + r * M + q, C)] = P(a[r][q]);
 }
 
+// The filter's second output plane.  FP64 storage keeps the information
+// vector v = S m.  FP32 storage keeps the filter mean m instead: rounding v to
+// FP32 perturbs it by about eps32 |S| |m|, and S^{-1} spreads that over every
+// component of the mean, so a small component (a velocity near zero beside
+// positions far from the origin) loses its relative precision; the rounded
+// mean keeps each component's own.  Readers rebuild v = S m from the rounded
+// S and m in the arithmetic type (then S^{-1} v is the stored mean up to
+// arithmetic rounding).
+template <typename TS>
+constexpr bool kStoreMean = sizeof(TS) < sizeof(double);
+
+// value to store in the plane for the state with information form (S, v)
+template <typename TS, typename T, int N>
+MS_DEVONLY void filter_plane_out(const T (&S)[N][N], const T (&v)[N], T (&o)[N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) o[r] = v[r];
+  if constexpr (kStoreMean<TS>) {
+    T Ls[N][N], ds[N];
+    chol(S, Ls, ds);
+    trsv_lower(Ls, ds, o);
+    trsv_upper_t(Ls, ds, o);
+  }
+}
+// v from the stored plane value (in place) and the state's S
+template <typename TS, typename T, int N>
+MS_DEVONLY void filter_plane_in(const T (&S)[N][N], T (&v)[N]) {
+  if constexpr (kStoreMean<TS>) {
+    T m[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) m[r] = v[r];
+    mv(S, m, v);
+  }
+}
+
 // Per-lane workspace (the in-tile prefixes) is blocked by tile like the state
 // arrays: component c of lane g sits at ((g / 64) * C + c) * 64 + g % 64, so a
 // wavefront writes its own contiguous C * 512 bytes, one full 512-byte run per
@@ -1379,8 +1413,12 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           for (int r = 0; r < N; ++r) v[r] = vn[r];
         }
         tstore_sym<TS, T, N, kTraj || kSuf>(So, Sym<N>::n, i, S);
-        tstore_vec<TS, T, N, kTraj || kSuf>(vo, N, i, v);
-        if (ws.status) bad = bad | nonfinite_vd(v, S);
+        {
+          T vs[N];
+          filter_plane_out<TS>(S, v, vs);
+          tstore_vec<TS, T, N, kTraj || kSuf>(vo, N, i, vs);
+          if (ws.status) bad = bad | nonfinite_vd(vs, S);
+        }
         if (kMode == kModeFilter && mo != nullptr) {
           T Pm[N][N], mm_[N];
           spd_inv(S, Pm);
@@ -1392,6 +1430,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         // trajectory maps from stored filter moments
         tload_sym(So, Sym<N>::n, i, S);
         tload_vec(vo, N, i, v);
+        filter_plane_in<TS>(S, v);
       }
       if constexpr (!kFilter) {
         // map of state i needs the element of state i+1
@@ -1668,6 +1707,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       T S[N][N], v[N];
       sym_from_raw<TS, T, N>(q.S, S);
       vec_from_raw(q.v, v);
+      filter_plane_in<TS>(S, v);
       const typename Cursor<TS, T, M>::Raw rc = q.r;
       if (cur.is_last(i)) {
         spd_inv(S, P);
@@ -1932,6 +1972,7 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
     T S[N][N], v[N];
     sym_from_raw<TS, T, N>(q.S, S);
     vec_from_raw(q.v, v);
+    filter_plane_in<TS>(S, v);
     two_filter_point<T, N, kCov>(S, v, s, x, P);
     tstore_vec(xo, N, i, x);
     if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);

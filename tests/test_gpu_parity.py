@@ -113,7 +113,8 @@ def _check_linear(case, dtype, chunk):
     S = sym_full(ms, r["S"], nx)
     v = planes_T(r["v"])
     Sref = np.linalg.inv(o["P"])
-    vref = np.einsum("kij,kj->ki", Sref, o["m"])
+    # the second filter plane: v = S m with FP64 storage, the mean m with FP32
+    vref = np.einsum("kij,kj->ki", Sref, o["m"]) if dtype == "f64" else o["m"]
     e_S = rel_err(S, Sref)
     e_v = rel_err(v, vref)
     ll = r["loglik"].cpu().numpy()
@@ -168,7 +169,7 @@ def test_nonlinear_iterates_parity(model, dtype):
     p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype])
     r = ms.iterated_nonlinear(p, wl.n_iter, covariances=True, loglik=True, objective=True)
     torch.cuda.synchronize()
-    tol = TOL[dtype] * (10 if dtype == "f32" else 1)
+    tol = TOL[dtype]
     e_xs = rel_err(planes_T(r["xs"]), o["xs"])
     e_xb = rel_err(planes_T(r["xbar"]), o["xbar"].T)
     e_Ps = rel_err(sym_full(ms, r["Ps"], wl.nx), o["Ps"])
