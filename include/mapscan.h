@@ -211,6 +211,21 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
                       double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* map_smooth without a caller-owned workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * map_smooth; the workspace is a fixed 64 MiB device array inside the library
+ * (one per device, held until the process ends), so nothing is allocated or
+ * freed.  Problems whose workspace (map_workspace_bytes at the schedule the
+ * library resolves) exceeds 64 MiB are rejected with MAP_E_WORKSPACE before
+ * anything is launched; a 2^20-step nx = 4 problem fits.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  Each
+ * call first clears the array's control words with a kernel on `stream`. */
+map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                              double* loglik, double* obj, double* g_loglik, double* g_obj,
+                              void* stream);
+
 /* Two-filter smoother (Sec. 4.3, eq. twofilter): the same MAP trajectory as
  * map_smooth, recovered the paper's second way.  The filter scan gives the
  * forward value function (S_k, v_k); a reverse segmented scan with the same

@@ -15,7 +15,7 @@ STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: 
 
 # every symbol include/mapscan.h declares
 EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "map_filter_scan",
-           "map_smoother_scan", "map_smooth", "map_two_filter_smooth", "map_iterated_nonlinear",
+           "map_smoother_scan", "map_smooth", "map_smooth_noalloc", "map_two_filter_smooth", "map_iterated_nonlinear",
            "map_backward",
            "map_autotune", "map_lti_exact_terms", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
            "map_last_error", "map_abi_version"]
@@ -73,6 +73,7 @@ def load(path: str | None = None):
     lib.map_filter_scan.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_smoother_scan.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_smooth.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
+    lib.map_smooth_noalloc.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp]
     lib.map_two_filter_smooth.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_iterated_nonlinear.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, sz, vp]

@@ -15,6 +15,12 @@
 #include "runner.h"
 #include "lti.h"
 
+// Fixed workspace of map_smooth_noalloc (one copy per device, held until the
+// process ends).  64 MiB fits the fused step of a 2^20-step nx = 4 problem at
+// the schedules the library picks for it.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace ms {
 
 __global__ void k_clear_words(unsigned int* w, int n) {
@@ -267,6 +273,35 @@ map_status finish_check(const map_problem& p, void* ws, hipStream_t st, map_stat
   return MAP_OK;
 }
 
+// ---------------------------------------------------------------- fixed scratch
+// Workspace of map_smooth_noalloc: the file-scope device array `scratch`
+// (below the includes) instead of a caller-owned buffer.  Host code never
+// uses the array's name as an address (on the host it only names the
+// symbol): the address on each device is looked up once, with that device
+// current, and kept.
+namespace scr {
+static std::mutex g_mu;
+static std::map<int, void*> g_ptr;  // device -> address of `scratch` there
+}  // namespace scr
+
+map_status scratch_address(void** out) {
+  int dev = 0;
+  map_status s = hip_status(hipGetDevice(&dev), "map_smooth_noalloc: hipGetDevice");
+  if (s != MAP_OK) return s;
+  std::lock_guard<std::mutex> lk(scr::g_mu);
+  auto it = scr::g_ptr.find(dev);
+  if (it == scr::g_ptr.end()) {
+    void* ptr = nullptr;
+    s = hip_status(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                   "map_smooth_noalloc: hipGetSymbolAddress");
+    if (s != MAP_OK) return s;
+    if (ptr == nullptr) return fail(MAP_E_HIP, "map_smooth_noalloc: scratch has no address");
+    it = scr::g_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return MAP_OK;
+}
+
 map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
   const size_t need =
       ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), sched::resolve(p)).total;
@@ -384,6 +419,32 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoSmooth{*p, a}));
+}
+
+map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                              double* loglik, double* obj, double* g_loglik, double* g_obj,
+                              void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
+    return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  const int chunk = sched::resolve(*p);
+  const size_t need = ws_layout(p->nx, p->n_steps + p->n_seg, compute_bytes(p->dtype), chunk).total;
+  if (need > kScratchBytes)
+    return fail(MAP_E_WORKSPACE,
+                "map_smooth_noalloc: the problem needs %zu bytes of workspace, the fixed scratch "
+                "holds %zu; use map_smooth with a caller-owned workspace",
+                need, kScratchBytes);
+  void* ws = nullptr;
+  if ((s = scratch_address(&ws)) != MAP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the control words must start at zero: cleared by a kernel (no memset)
+  // before every call, also after a call that failed part-way
+  k_clear_words<<<1, 256, 0, st>>>(static_cast<unsigned int*>(ws), kCounterWords);
+  if ((s = hip_status(hipGetLastError(), "map_smooth_noalloc: clear")) != MAP_OK) return s;
+  SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws, st, chunk};
+  return finish_check(*p, ws, st, dispatch(*p, DoSmooth{*p, a}));
 }
 
 map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps,
