@@ -42,6 +42,20 @@
 
 #define MX 8
 
+/* Running sum with Neumaier's compensation: the per-segment log-likelihood
+ * and objective are sums of one term per step; over 2^20 steps a plain
+ * running sum carries a rounding error of order sqrt(T) eps |sum|, which
+ * changes erratically with the inputs.  The compensated sum stays within a
+ * few eps of the exact sum of the computed terms. */
+typedef struct { double s, c; } ksum;
+static void ksum_add(ksum *k, double x) {
+  const double t = k->s + x;
+  if (fabs(k->s) >= fabs(x)) k->c += (k->s - t) + x;
+  else k->c += (x - t) + k->s;
+  k->s = t;
+}
+static double ksum_value(const ksum *k) { return k->s + k->c; }
+
 /* ---------- small dense helpers (row-major, n <= 8) ---------- */
 
 static void mm(int n, int m, int p, const double *a, const double *b, double *c) {
@@ -185,7 +199,7 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
     double *xs = xs_out + x0 * nx, *Ps = Ps_out + x0 * n2;
     memcpy(m, m0 + s * m0_seg, sizeof(double) * nx);
     memcpy(P, P0 + s * P0_seg, sizeof(double) * n2);
-    double ll = 0.0;
+    ksum ll = {0.0, 0.0};
 
     /* ---- forward: covariance-form Kalman filter ---- */
     for (long j = 1; j <= T; ++j) {
@@ -225,7 +239,7 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
       chol_solve(ny, 1, Ls, z);
       double quad = 0.0;
       for (int i = 0; i < ny; ++i) quad += e[i] * z[i];
-      ll += -0.5 * (ny * LOG2PI + ld + quad);
+      ksum_add(&ll, -0.5 * (ny * LOG2PI + ld + quad));
       /* K^T = Sg^{-1} H P-  (Sg symmetric) */
       double KT[MX * MX];
       memcpy(KT, HP, sizeof(double) * ny * nx);
@@ -247,7 +261,7 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
         }
       symmetrize(nx, Pj);
     }
-    loglik_out[s] = ll;
+    loglik_out[s] = ksum_value(&ll);
 
     /* ---- backward: discrete RTS smoother ---- */
     memcpy(xs + T * nx, m + T * nx, sizeof(double) * nx);
@@ -281,14 +295,16 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
     }
 
     /* ---- discretised OM objective at xs ---- */
-    double M = 0.0;
+    ksum M = {0.0, 0.0};
     {
       double Lq[MX * MX], dx[MX], z[MX];
       if (!chol(nx, P0 + s * P0_seg, Lq)) { free(mp); free(Pp); return -(s + 1); }
       for (int i = 0; i < nx; ++i) dx[i] = xs[i] - m0[s * m0_seg + i];
       memcpy(z, dx, sizeof(double) * nx);
       chol_solve(nx, 1, Lq, z);
-      for (int i = 0; i < nx; ++i) M += 0.5 * dx[i] * z[i];
+      double m0t = 0.0;
+      for (int i = 0; i < nx; ++i) m0t += 0.5 * dx[i] * z[i];
+      ksum_add(&M, m0t);
     }
     for (long j = 1; j <= T; ++j) {
       const long k = k0 + j - 1;
@@ -319,7 +335,8 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
       if (!chol(nw, Wh, Lw)) { free(mp); free(Pp); return -(s + 1); }
       memcpy(z, LtD, sizeof(double) * nw);
       chol_solve(nw, 1, Lw, z);
-      for (int a = 0; a < nw; ++a) M += 0.5 * LtD[a] * z[a];
+      double mk = 0.0;
+      for (int a = 0; a < nw; ++a) mk += 0.5 * LtD[a] * z[a];
       /* measurement: (h/2) eps^T R^{-1} eps */
       double Hx[MX], eps[MX], LR[MX * MX];
       mv(ny, nx, Hk, xj, Hx);
@@ -327,9 +344,10 @@ long oracle_smooth(int nx, int ny, int nw, long n_seg, const long *seg_off,
       if (!chol(ny, Rk, LR)) { free(mp); free(Pp); return -(s + 1); }
       memcpy(z, eps, sizeof(double) * ny);
       chol_solve(ny, 1, LR, z);
-      for (int i = 0; i < ny; ++i) M += 0.5 * h * eps[i] * z[i];
+      for (int i = 0; i < ny; ++i) mk += 0.5 * h * eps[i] * z[i];
+      ksum_add(&M, mk);
     }
-    mstar_out[s] = M;
+    mstar_out[s] = ksum_value(&M);
   }
   free(mp);
   free(Pp);

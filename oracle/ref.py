@@ -176,3 +176,13 @@ def gradients(model, nx, seg, xbar):
     gl, = torch.autograd.grad(out["loglik"], th, retain_graph=True)
     gm, = torch.autograd.grad(out["mstar"], th)
     return gl, gm, out
+
+
+def trajectory_vjp(model, nx, seg, xbar, w):
+    """d (sum_k w_k . xs_k) / d theta by autograd of the plain definitions
+    above (w [T+1, nx] a fixed cotangent of the MAP trajectory), linearisation
+    point xbar [T+1, nx] held fixed."""
+    th = seg["theta"].clone().requires_grad_(True)
+    out = smooth_segment(model, th, xbar.detach(), seg["dt"], seg["y"], seg["m0"], seg["P0"], nx)
+    g, = torch.autograd.grad((out["xs"] * w).sum(), th)
+    return g

@@ -188,6 +188,41 @@ def test_gradients_autograd_vs_dense_finite_differences(gamma):
         assert abs(gm[i].item() - fd_m) <= 1e-6 * max(1.0, abs(fd_m)), (i, gm[i].item(), fd_m)
 
 
+def _dense_mean_theta(wl, theta, xbar=None):
+    w = workloads.Workload(**{**wl.__dict__})
+    w.theta = theta[None]
+    return _dense.dense_posterior(w, 0, xbar)[0]
+
+
+@pytest.mark.parametrize("model", ["cv", "vdp"])
+def test_trajectory_vjp_vs_dense_finite_differences(model):
+    """Oracle VJP of the MAP trajectory (autograd through the KF/RTS
+    definitions) against central differences of the dense posterior mean
+    (Gaussian conditioning of the whole discrete model), w . dx*/dtheta for a
+    random cotangent w; Van der Pol with its linearisation point held fixed."""
+    if model == "cv":
+        wl = workloads.cv(T=25, d=2, dt=0.05, gamma=0.3, q=0.5, r=0.05, m0=[5, 5, 0, 0],
+                          P0=1e-2 * np.eye(4), seed=52)
+        xbar = np.zeros((4, 26))
+    else:
+        wl = workloads.vdp(T=25, dt=0.02, seed=53, n_iter=2)
+        xbar = cref.iterate(wl, n_iter=1)["xs"].T.copy()
+    nx = wl.nx
+    rng = np.random.default_rng(54)
+    wv = rng.normal(size=(wl.n_states, nx))
+    seg = ref.workload_segment(wl, 0)
+    g = ref.trajectory_vjp(model, nx, seg, torch.tensor(xbar.T.copy()),
+                           torch.tensor(wv)).numpy()
+    th = wl.theta[0].copy()
+    for i in range(th.size):
+        h = 1e-5 * max(1.0, abs(th[i]))
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = ((_dense_mean_theta(wl, tp, xbar) - _dense_mean_theta(wl, tm, xbar)) * wv).sum() / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
+
+
 def test_nonlinear_iteration_matches_nonlinear_least_squares():
     """Gauss--Newton (Sec. 4.4) on Van der Pol (Q invertible) converges to the
     minimiser of the nonlinear discretised objective found by a generic
