@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 5
+#define MAPSCAN_ABI_VERSION 6
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
 
@@ -256,13 +256,30 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
                                   double* loglik, double* obj, double* g_loglik, double* g_obj,
                                   void* ws, size_t ws_bytes, void* stream);
 
-/* Adjoint from saved filter moments (checkpointing: elements and trajectory
- * are recomputed, nothing else is stored): reverse-scans the same elements to
- * rebuild xs and Ps (written to the caller's buffers) and accumulates
- * g_loglik and g_obj ([n_seg][n_theta] double) as in map_smooth. */
+/* Adjoint from saved filter moments.  Elements are recomputed from the
+ * inputs (never stored); the filter's S and v planes (map_filter_scan or
+ * map_smooth) are read.  Reverse-scans the same elements to rebuild xs and
+ * Ps (written to the caller's buffers) and accumulates, per segment
+ * ([n_seg][n_theta] double, each optional):
+ *   g_loglik, g_obj  d loglik / d theta (Fisher identity) and d obj / d theta
+ *                    (envelope theorem), as map_smooth;
+ *   g_xs_theta       with g_xs (tiled [nx] per state, the cotangent dl/dx* of
+ *                    a scalar l of the trajectory): dl/dtheta by the implicit
+ *                    function theorem.  x* is the stationary point of the
+ *                    discretised objective (Sec. 2.1 eq. OM, Sec. 4.4), so
+ *                    dl/dtheta = -mu^T d(grad_x M_d)/dtheta with mu = H^{-1} g
+ *                    (H the objective's Hessian in x): mu solves the same
+ *                    scan problem with every element's b set to 0 and eta to
+ *                    g (three more passes), then the per-step cotangents of
+ *                    A, b, C, R are reduced per segment.  mu (out, tiled [nx]
+ *                    per state) receives mu, vmu (out, tiled [nx] per state)
+ *                    the adjoint problem's second filter plane; both must be
+ *                    distinct from xs, S, v and g_xs.
+ * For nonlinear models every gradient holds the linearisation point
+ * p->xbar fixed.  At least one of g_loglik, g_obj, g_xs must be given. */
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
-                        double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
-                        void* stream);
+                        double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
+                        void* vmu, double* g_xs_theta, void* ws, size_t ws_bytes, void* stream);
 
 /* Schedule autotuner for the batched segmented scan (spec item: tile
  * size per problem shape).  Times the fused step (map_smooth with every
@@ -311,7 +328,9 @@ map_status map_schedule(const map_problem* p, int32_t* chunk_out);
  * Kinds: 0 filter up-sweep, 1 filter fix-up, 2 fused filter fix-up +
  * trajectory up-sweep, 3 trajectory up-sweep from stored S, v, 4 trajectory
  * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing), 7 filter
- * fix-up + backward-filter up-sweep (two-filter), 8 two-filter combination. */
+ * fix-up + backward-filter up-sweep (two-filter), 8 two-filter combination,
+ * 9 the adjoint problem's passes (implicit-function VJP), 10 its per-step
+ * cotangent reduction. */
 map_status map_profile_enable(int32_t capacity);
 map_status map_profile_reset(void);
 map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms);

@@ -399,20 +399,33 @@ def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, lo
                         g_obj=gm), natural)
 
 
-def backward(p: Problem, S, v, covariances=True, objective=True, natural=True):
-    """Adjoint from saved (tiled) filter moments: recomputes the trajectory and
-    returns d loglik / d theta and d obj / d theta per segment."""
+def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, loglik_grad=True,
+             obj_grad=True, g_xs=None):
+    """Adjoint from saved (tiled) filter planes S, v: recomputes the trajectory
+    and returns d loglik / d theta and d obj / d theta per segment (when
+    asked), and with `g_xs` (a cotangent of x*: natural [nx, n_states] or a
+    tiled buffer) d(l)/d theta by the implicit function theorem (`g_xs_theta`)
+    together with mu = H^{-1} g_xs."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
     xs = p._tiled(p.nx)
     Ps = p._tiled(p.nsym) if covariances else None
     obj = p._empty(p.n_seg, dtype=f64) if objective else None
-    gl = p._empty(p.n_seg, p.n_theta, dtype=f64)
-    gm = p._empty(p.n_seg, p.n_theta, dtype=f64)
+    gl = p._empty(p.n_seg, p.n_theta, dtype=f64) if loglik_grad else None
+    gm = p._empty(p.n_seg, p.n_theta, dtype=f64) if obj_grad else None
+    gx = mu = vmu = gxt = None
+    if g_xs is not None:
+        g = g_xs.to(p.device, p.dtype)
+        gx = to_tiled(g.reshape(p.nx, p.n_states)) if g.dim() == 2 else g.contiguous()
+        mu = p._tiled(p.nx)
+        vmu = p._tiled(p.nx)
+        gxt = p._empty(p.n_seg, p.n_theta, dtype=f64)
     _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
-                                _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(), _stream()))
-    return _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm), natural)
+                                _ptr(obj), _ptr(gl), _ptr(gm), _ptr(gx), _ptr(mu), _ptr(vmu),
+                                _ptr(gxt), _ptr(ws), ws.numel(), _stream()))
+    return _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm, mu=mu, g_xs_theta=gxt),
+                natural)
 
 
 class GraphedSmooth:
@@ -473,27 +486,39 @@ class MapSmooth(torch.autograd.Function):
     The forward pass runs the fused scans with the adjoint enabled, so the
     gradients of loglik (Fisher identity) and obj (envelope theorem) with
     respect to theta come out of the same pass; backward scales them by the
-    incoming cotangents.  A cotangent on xs (implicit-function VJP) is not
-    provided and raises."""
+    incoming cotangents.  A cotangent on xs (natural [nx, n_states]) goes
+    through `map_backward`'s implicit-function VJP, which reads the filter
+    planes S, v kept from the forward pass.  theta is [n_seg, n_theta]
+    (per segment), or [n_theta] / [1, n_theta] shared by every segment (its
+    gradient is then the sum over segments).  Nonlinear models are
+    linearised about the problem's xbar, held fixed."""
 
     @staticmethod
     def forward(ctx, theta, problem: Problem):
         problem.set_theta(theta.detach())
-        r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True, natural=True)
-        ctx.save_for_backward(r["g_loglik"], r["g_obj"])
+        r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True,
+                   natural=False)
+        ctx.problem = problem
+        ctx.save_for_backward(r["g_loglik"], r["g_obj"], r["S"], r["v"], theta.detach().clone())
         ctx.theta_shape = theta.shape
         ctx.theta_dtype = theta.dtype
-        ctx.mark_non_differentiable(r["xs"])
-        return r["xs"], r["loglik"], r["obj"]
+        return problem.natural(r["xs"], problem.nx), r["loglik"], r["obj"]
 
     @staticmethod
     def backward(ctx, g_xs, g_ll, g_obj):
-        gl, gm = ctx.saved_tensors
+        gl, gm, S, v, theta = ctx.saved_tensors
         g = torch.zeros_like(gl)
         if g_ll is not None:
             g = g + g_ll[:, None] * gl
         if g_obj is not None:
             g = g + g_obj[:, None] * gm
-        if ctx.theta_shape != g.shape:
-            g = g.sum(0) if len(ctx.theta_shape) == 1 else g
+        if g_xs is not None and bool((g_xs != 0).any()):
+            p = ctx.problem
+            p.set_theta(theta)   # the forward pass's theta (the problem may have moved on)
+            r = backward(p, S, v, covariances=False, objective=False, natural=False,
+                         loglik_grad=False, obj_grad=False, g_xs=g_xs)
+            g = g + r["g_xs_theta"]
+        if tuple(ctx.theta_shape) != tuple(g.shape):
+            # one theta shared by every segment ([n_theta] or [1, n_theta])
+            g = g.sum(0, keepdim=True)
         return g.to(ctx.theta_dtype).reshape(ctx.theta_shape), None

@@ -20,7 +20,8 @@ EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "m
            "map_autotune", "map_lti_exact_terms", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
            "map_last_error", "map_abi_version"]
 PROF_KINDS = {"filter_up": 0, "filter_down": 1, "fused_down": 2, "traj_up": 3, "traj_down": 4,
-              "traj_down_adjoint": 5, "aux": 6, "two_filter_up": 7, "two_filter_down": 8}
+              "traj_down_adjoint": 5, "aux": 6, "two_filter_up": 7, "two_filter_down": 8,
+              "ift_solve": 9, "ift_grad": 10}
 
 
 class MapProblem(ctypes.Structure):
@@ -76,7 +77,7 @@ def load(path: str | None = None):
     lib.map_smooth_noalloc.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp]
     lib.map_two_filter_smooth.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_iterated_nonlinear.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
-    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, sz, vp]
+    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_autotune.argtypes = [P, vp, sz, ctypes.c_char_p, ctypes.POINTER(i32), vp]
     lib.map_schedule.argtypes = [P, ctypes.POINTER(i32)]
     lib.map_lti_exact_terms.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]

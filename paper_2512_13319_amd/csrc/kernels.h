@@ -560,6 +560,7 @@ struct Cursor {
     TS dt;
     TS y[NY];
     TS xb[M::kNonlinear ? NX : 1];
+    TS g[M::kIft ? NX : 1];  // cotangent of x* at the state (adjoint problem)
     MS_DEVONLY void meas(T (&o)[NY]) const {
 #pragma unroll
       for (int c = 0; c < NY; ++c) o[c] = T(y[c]);
@@ -572,6 +573,30 @@ struct Cursor {
     if constexpr (M::kNonlinear) {
 #pragma unroll
       for (int c = 0; c < NX; ++c) r.xb[c] = p.xbar[tix(i, c, NX)];
+    }
+    if constexpr (M::kIft) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) r.g[c] = p.gx[tix(i, c, NX)];
+    }
+  }
+
+  // Adjoint problem (Ift<M>): the fresh element of the step ending at the
+  // fetched state has b = 0 and eta = g there; the prior's eta is g at the
+  // segment's first state.  No-ops for every other model.
+  template <int NW_>
+  MS_DEVONLY void ift_fresh(const Raw& r, Fresh<T, NX, NW_>& f) const {
+    if constexpr (M::kIft) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        f.b[c] = T(0);
+        f.eta[c] = T(r.g[c]);
+      }
+    }
+  }
+  MS_DEVONLY void ift_prior(const Raw& r, T (&v0)[NX]) const {
+    if constexpr (M::kIft) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v0[c] = T(r.g[c]);
     }
   }
 
@@ -1167,6 +1192,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
         if (cur.is_head(i)) {
           T m0[N], P0i[N][N];
           cur.prior(p, agg.J, agg.eta, m0, P0i);
+          cur.ift_prior(rc, agg.eta);
           mzero(agg.A);
           mzero(agg.C);
 #pragma unroll
@@ -1178,6 +1204,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
           rc.meas(y);
           Fresh<T, N, M::NW> f;
           fresh_from_step(st, y, f);
+          cur.ift_fresh(rc, f);
           fold_fresh(agg, f);
         }
         if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
@@ -1384,6 +1411,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           }
           T m0[N], P0i[N][N];
           cur.prior(p, S, v, m0, P0i);
+          cur.ift_prior(rc, v);
           if constexpr (kSuf) pf = T(1);
         } else {
           Step<T, N, NY, NW> st;
@@ -1392,6 +1420,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           cur.terms(p, i, rc, st);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
+          cur.ift_fresh(rc, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           if (kTraj && !first) {
             info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
@@ -1412,7 +1441,8 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
 #pragma unroll
           for (int r = 0; r < N; ++r) v[r] = vn[r];
         }
-        tstore_sym<TS, T, N, kTraj || kSuf>(So, Sym<N>::n, i, S);
+        // the adjoint problem's S is the original problem's (stored by its pass)
+        if constexpr (!M::kIft) tstore_sym<TS, T, N, kTraj || kSuf>(So, Sym<N>::n, i, S);
         {
           T vs[N];
           filter_plane_out<TS>(S, v, vs);
@@ -1447,6 +1477,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           rc.meas(y);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
+          cur.ift_fresh(rc, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           aff_append(sagg, G, beta, Lam);
@@ -1472,6 +1503,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         rn.meas(y);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
+        cur.ift_fresh(rn, f);
         T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
         info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
         aff_append(sagg, G, beta, Lam);
@@ -1668,8 +1700,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
   dstr[0] = 1;
 #pragma unroll
   for (int t = 0; t < NTH; ++t) {
-    dst[1 + t] = (kGrad && M::NTH > 0) ? acc.g_loglik + t : nullptr;
-    dst[1 + NTH + t] = (kGrad && M::NTH > 0) ? acc.g_obj + t : nullptr;
+    dst[1 + t] = (kGrad && M::NTH > 0 && acc.g_loglik) ? acc.g_loglik + t : nullptr;
+    dst[1 + NTH + t] = (kGrad && M::NTH > 0 && acc.g_obj) ? acc.g_obj + t : nullptr;
     dstr[1 + t] = dstr[1 + NTH + t] = NTH;
   }
   int64_t seg_acc = -1;
@@ -1719,6 +1751,7 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
         cur.terms(p, i + 1, rc, st);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
+        cur.ift_fresh(rc, f);
         // trajectory map of state i (shares Z with the information step)
         T W[N][NW];
         mm(S, f.V, W);
@@ -2005,6 +2038,123 @@ __global__ void __launch_bounds__(kBlock) k_two_filter_down(Prob<TS> p, Ws<T> ws
     q0 = q1;
   }
   report_nonfinite(ws.status, bad);
+}
+
+// --------------------------------------------------------------------------- IFT
+// Implicit-function VJP: the gradient with respect to theta of a scalar
+// l(x*) of the trajectory, given its cotangent g = dl/dx* at every state.
+// x* is the stationary point of the discretised objective M_d(x; theta), so
+// dx*/dtheta = -H^{-1} d(grad_x M_d)/dtheta with H the (symmetric) Hessian
+// of M_d in x, and
+//   dl/dtheta = -d/dtheta [mu^T grad_x M_d(x*; theta)],   mu = H^{-1} g,
+// with x* and mu held fixed.  mu minimises 1/2 mu^T H mu - g^T mu: the
+// problem Ift<M> (same elements with b = 0 and eta = g), solved by the
+// smoother's kernels.  Differentiating the element terms
+// 1/2 x_k^T J x_k - x_k^T eta + 1/2 |x_{k-1} - A x_k - b|^2_{C^{-1}} of
+// mu^T grad_x M_d gives, per step k, the cotangents of the element
+//   A: lam mu_k^T + nu x*_k^T,   b: nu,   C: (nu lam^T + lam nu^T) / 2,
+//   R (through J = dt H^T R^{-1} H and eta = dt H^T R^{-1} (y - r)):
+//      -dt (R^{-1} eps (R^{-1} H mu_k)^T + its transpose) / 2,
+// with lam = C^{-1}(x*_{k-1} - A x*_k - b) = v_{k-1} - S_{k-1} x*_{k-1}, the
+// costate of the problem, nu = v'_{k-1} - S_{k-1} mu_{k-1} that of the adjoint
+// problem (v' its filter vector) and eps = y_k - r_k - H x*_k; no C^{-1} is
+// formed, so Q may be singular.  The model's vjp maps them to theta (the
+// prior has no theta).  One lane per run of kRow consecutive states, per-
+// segment sums reduced over the block.
+struct IftIn {
+  const void* S;    // filter information matrices of the problem
+  const void* v;    // its second filter plane (v, or m with FP32 storage)
+  const void* vmu;  // the adjoint problem's second filter plane
+  const void* xs;   // x*
+  const void* mu;   // mu = H^{-1} g
+};
+
+template <typename TS, typename T, class M>
+__global__ void __launch_bounds__(kBlock) k_ift_grad(Prob<TS> p, IftIn in, double* gout) {
+  constexpr int N = M::NX, NY = M::NY, NW = M::NW, NTH = M::NTH;
+  const TS* Si = static_cast<const TS*>(in.S);
+  const TS* vi = static_cast<const TS*>(in.v);
+  const TS* gi = static_cast<const TS*>(in.vmu);
+  const TS* xi = static_cast<const TS*>(in.xs);
+  const TS* mi = static_cast<const TS*>(in.mu);
+  const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t ns = p.n_states;
+  const int64_t j0 = g * kRow, j1 = j0 + kRow < ns ? j0 + kRow : ns;
+  double val[NTH];
+#pragma unroll
+  for (int t = 0; t < NTH; ++t) val[t] = 0.0;
+  double* dst[NTH];
+  int64_t dstr[NTH];
+#pragma unroll
+  for (int t = 0; t < NTH; ++t) {
+    dst[t] = gout + t;
+    dstr[t] = NTH;
+  }
+  int64_t seg_acc = -1;
+  if (j0 < j1) {
+    Cursor<TS, T, M> cur;
+    cur.init(p, j0);
+    seg_acc = cur.s;
+    for (int64_t i = j0; i < j1; ++i) {
+      if (cur.s != seg_acc) {
+        flush_lane<NTH>(seg_acc, val, dst, dstr);
+        seg_acc = cur.s;
+      }
+      if (!cur.is_head(i)) {
+        typename Cursor<TS, T, M>::Raw r;
+        cur.fetch(p, i, r);
+        Step<T, N, NY, NW> st;
+        cur.terms(p, i, r, st);
+        T y[NY];
+        r.meas(y);
+        T S[N][N], v[N], vg[N], xp[N], xk[N], mp[N], mk[N];
+        tload_sym(Si, Sym<N>::n, i - 1, S);
+        tload_vec(vi, N, i - 1, v);
+        filter_plane_in<TS>(S, v);
+        tload_vec(gi, N, i - 1, vg);
+        filter_plane_in<TS>(S, vg);
+        tload_vec(xi, N, i - 1, xp);
+        tload_vec(xi, N, i, xk);
+        tload_vec(mi, N, i - 1, mp);
+        tload_vec(mi, N, i, mk);
+        T Sx[N], Sm[N], lam[N], nu[N];
+        mv(S, xp, Sx);
+        mv(S, mp, Sm);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          lam[a] = v[a] - Sx[a];
+          nu[a] = vg[a] - Sm[a];
+        }
+        T GA[N][N], Gb[N], GC[N][N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          Gb[a] = nu[a];
+#pragma unroll
+          for (int b = 0; b < N; ++b) {
+            GA[a][b] = lam[a] * mk[b] + nu[a] * xk[b];
+            GC[a][b] = T(0.5) * (nu[a] * lam[b] + lam[a] * nu[b]);
+          }
+        }
+        T Hx[NY], Hm[NY], eps[NY], Re[NY], Rm[NY];
+        mv(st.H, xk, Hx);
+        mv(st.H, mk, Hm);
+#pragma unroll
+        for (int a = 0; a < NY; ++a) eps[a] = y[a] - st.r[a] - Hx[a];
+        mv(st.Rinv, eps, Re);
+        mv(st.Rinv, Hm, Rm);
+        T GR[NY][NY];
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+#pragma unroll
+          for (int b = 0; b < NY; ++b) GR[a][b] = T(-0.5) * st.dt * (Re[a] * Rm[b] + Rm[a] * Re[b]);
+        T xb[N];
+        cur.xbar(p, i, xb);
+        M::vjp(cur.th, xb, st.dt, GA, Gb, GC, GR, val);
+      }
+      if (cur.is_last(i) && i + 1 < ns) cur.next(p);
+    }
+  }
+  flush_block<NTH>(seg_acc, val, dst, dstr);
 }
 
 // --------------------------------------------------------------------------- misc

@@ -348,6 +348,14 @@ struct DoTwoFilter {
     return hip_status(Runner<TS, T, M>::two_filter(p, a), "map_two_filter_smooth");
   }
 };
+struct DoIft {
+  const map_problem& p;
+  SmoothArgs a;
+  IftArgs b;
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::ift(p, a, b), "map_backward (implicit-function VJP)");
+  }
+};
 struct DoInitX {
   const map_problem& p;
   void* xb;
@@ -502,17 +510,32 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
 }
 
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
-                        double* obj, double* g_loglik, double* g_obj, void* ws, size_t ws_bytes,
-                        void* stream) {
+                        double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
+                        void* vmu, double* g_xs_theta, void* ws, size_t ws_bytes, void* stream) {
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
-  if (g_loglik == nullptr || g_obj == nullptr) return fail(MAP_E_ARG, "g_loglik/g_obj is NULL");
+  if (g_loglik == nullptr && g_obj == nullptr && g_xs == nullptr)
+    return fail(MAP_E_ARG, "nothing to differentiate: g_loglik, g_obj and g_xs are NULL");
+  if (g_xs != nullptr) {
+    if (mu == nullptr || vmu == nullptr || g_xs_theta == nullptr)
+      return fail(MAP_E_ARG, "g_xs needs mu, vmu and g_xs_theta");
+    const void* outs[3] = {xs, mu, vmu};
+    const void* ins[3] = {S, v, g_xs};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (outs[a] == ins[b] || (a < b && outs[a] == outs[b]))
+          return fail(MAP_E_ARG, "xs, mu and vmu must be distinct and not alias S, v or g_xs");
+  }
   if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               g_loglik, g_obj, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
-  return finish_check(*p, ws, a.stream, dispatch(*p, DoSmoother{*p, a, true}));
+               g_loglik, g_obj, ws, st, sched::resolve(*p)};
+  s = dispatch(*p, DoSmoother{*p, a, g_loglik != nullptr || g_obj != nullptr});
+  if (s == MAP_OK && g_xs != nullptr)
+    s = dispatch(*p, DoIft{*p, a, IftArgs{g_xs, mu, vmu, g_xs_theta}});
+  return finish_check(*p, ws, st, s);
 }
 
 map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const char* cache_path,

@@ -45,6 +45,7 @@ struct Prob {
   const T* theta;          // [n_seg][n_theta] (stride 0: shared)
   int64_t th_stride;
   const T* xbar;           // [nx][n_states] linearisation states (nonlinear models)
+  const T* gx;             // [nx][n_states] cotangent of x* (the problem Ift<M> only)
   // general linear model: row-major per-step matrices, stride 0 = shared by all steps
   const T *F, *c, *L, *W, *H, *r, *R;
   int64_t sF, sc, sL, sW, sH, sr, sR;
@@ -59,6 +60,7 @@ struct ModelCV {
   static constexpr int NX = 2 * D, NY = D, NW = D, NTH = 3;
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = true;
+  static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = -1;  // no angular measurement component
 
   template <typename T>
@@ -112,6 +114,7 @@ struct ModelVdP {
   static constexpr int NX = 2, NY = 1, NW = 2, NTH = 3;
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
+  static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -161,6 +164,7 @@ struct ModelLorenz63 {
   static constexpr int NX = 3, NY = 3, NW = 3, NTH = 5;
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
+  static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -215,6 +219,7 @@ struct ModelLinear {
   static constexpr int NX = NX_, NY = NY_, NW = NW_, NTH = 0;
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = false;
+  static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = -1;
 };
 
@@ -234,6 +239,7 @@ struct ModelCT {
   static constexpr int NX = 5, NY = 2, NW = 3, NTH = 4;
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
+  static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = 1;
 
   template <typename T>
@@ -290,6 +296,18 @@ struct ModelCT {
     out[2] += double(GR[0][0]);
     out[3] += double(GR[1][1]);
   }
+};
+
+// ------------------------------------------------------------------ adjoint problem
+// The problem whose minimiser is mu = H^{-1} g, H the Hessian of the discretised
+// objective and g a cotangent of the trajectory x* (implicit-function VJP, see
+// k_ift_grad): the quadratic part of the objective is unchanged (same A, C, J
+// in every element) and its linear part is -g^T x, i.e. every fresh element has
+// b = 0 and eta = g_k, and the prior element eta = g_0 (its J stays P0^{-1}).
+// The scan kernels read g through Prob::gx when instantiated with Ift<M>.
+template <class M>
+struct Ift : M {
+  static constexpr bool kIft = true;
 };
 
 }  // namespace ms

@@ -93,6 +93,14 @@ struct SmoothArgs {
   int chunk;  // states per lane (4, 8, 16 or 32)
 };
 
+// Implicit-function VJP (map_backward with a cotangent of x*).
+struct IftArgs {
+  const void* gx;   // tiled [nx] per state: cotangent of x*
+  void* mu;         // out, tiled [nx] per state: mu = H^{-1} g
+  void* vmu;        // out, tiled [nx] per state: the adjoint problem's second filter plane
+  double* g_theta;  // out [n_seg][n_theta]
+};
+
 // Profiling hook: kernel kinds timed by HIP events when enabled.
 enum ProfKind : int {
   kProfFilterUp = 0,
@@ -104,7 +112,9 @@ enum ProfKind : int {
   kProfAux = 6,
   kProfTwoFilterUp = 7,
   kProfTwoFilterDown = 8,
-  kProfKinds = 9
+  kProfIftSolve = 9,
+  kProfIftGrad = 10,
+  kProfKinds = 11
 };
 void prof_begin(int kind, hipStream_t st);
 void prof_end(int kind, hipStream_t st);
@@ -117,6 +127,8 @@ struct Runner {
   static hipError_t smoother(const map_problem& p, const SmoothArgs& a, bool grad);
   static hipError_t smooth(const map_problem& p, const SmoothArgs& a);
   static hipError_t two_filter(const map_problem& p, const SmoothArgs& a);
+  // needs a.S, a.v (the filter planes) and a.xs (x*) of the problem
+  static hipError_t ift(const map_problem& p, const SmoothArgs& a, const IftArgs& b);
   static hipError_t init_xbar(const map_problem& p, void* xbar, hipStream_t st);
 };
 

@@ -22,6 +22,7 @@ inline Prob<T> make_prob(const map_problem& q) {
   p.theta = static_cast<const T*>(q.theta);
   p.th_stride = q.theta_stride;
   p.xbar = static_cast<const T*>(q.xbar);
+  p.gx = nullptr;
   p.F = static_cast<const T*>(q.F);
   p.c = static_cast<const T*>(q.c);
   p.L = static_cast<const T*>(q.L);
@@ -231,6 +232,46 @@ hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& 
     k_two_filter_down<TS, T, M, false><<<g, kBlock, 0, a.stream>>>(p, w, to);
   prof_end(kProfTwoFilterDown, a.stream);
   return hipGetLastError();
+}
+
+// Implicit-function VJP: mu = H^{-1} g by the smoother's three passes on the
+// adjoint problem Ift<M> (the problem's own S is read, not stored again), then
+// the per-step cotangents reduced per segment (k_ift_grad).
+template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::ift(const map_problem& q, const SmoothArgs& a, const IftArgs& b) {
+  if constexpr (!M::kAdjoint) {
+    return hipErrorInvalidValue;  // rejected by the entry point before this
+  } else {
+    using MI = Ift<M>;
+    Prob<TS> p = make_prob<TS>(q);
+    p.gx = static_cast<const TS*>(b.gx);
+    Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
+    const unsigned g = grid_for(w.n_tiles);
+    prof_begin(kProfIftSolve, a.stream);
+    // also zeroes g_theta (the accumulator of the last kernel)
+    k_filter_up<TS, T, MI><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
+        p, up_view(w), Acc{nullptr, nullptr, b.g_theta, nullptr});
+    prof_end(kProfIftSolve, a.stream);
+    MS_CHECK(hipGetLastError());
+    FilterOut fo{a.S, b.vmu, nullptr, nullptr, 0};
+    const Acc none{nullptr, nullptr, nullptr, nullptr};
+    prof_begin(kProfIftSolve, a.stream);
+    k_filter_down<TS, T, MI, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, none);
+    prof_end(kProfIftSolve, a.stream);
+    MS_CHECK(hipGetLastError());
+    TrajOut to{a.S, b.vmu, b.mu, nullptr, 0, 0};
+    prof_begin(kProfIftSolve, a.stream);
+    k_traj_down<TS, T, MI, false, false><<<g, kBlock, 0, a.stream>>>(p, w, to, none);
+    prof_end(kProfIftSolve, a.stream);
+    MS_CHECK(hipGetLastError());
+    IftIn in{a.S, a.v, b.vmu, a.xs, b.mu};
+    const int64_t lanes = (p.n_states + kRow - 1) / kRow;
+    prof_begin(kProfIftGrad, a.stream);
+    k_ift_grad<TS, T, M><<<unsigned((lanes + kBlock - 1) / kBlock), kBlock, 0, a.stream>>>(
+        p, in, b.g_theta);
+    prof_end(kProfIftGrad, a.stream);
+    return hipGetLastError();
+  }
 }
 
 #define MS_COMMA ,

@@ -183,8 +183,15 @@ def test_workspace_and_output_checks(seg):
                                None) == -1
     assert lib.map_smoother_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                  None) == -1
-    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE,
-                            1 << 40, None) == -1
+    # nothing to differentiate
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, None,
+                            None, None, FAKE, 1 << 40, None) == -1
+    # a cotangent of x* needs mu, vmu and the output, none of them aliasing the inputs
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, FAKE, None,
+                            FAKE + 64, FAKE + 128, FAKE, 1 << 40, None) == -1
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE + 8, FAKE + 16, None, None, None, None,
+                            FAKE + 24, FAKE + 16, FAKE + 32, FAKE + 40, FAKE, 1 << 40, None) == -1
+    assert b"distinct" in lib.map_last_error()
     assert lib.map_iterated_nonlinear(ctypes.byref(p), 0, None, FAKE, FAKE, FAKE, FAKE, None, None,
                                       None, None, None, FAKE, 1 << 40, None) == -1
     assert lib.map_iterated_nonlinear(ctypes.byref(p), 2, None, FAKE, FAKE, FAKE, FAKE, None, None,
@@ -204,8 +211,8 @@ def test_gradients_need_parametric_model():
         setattr(p, k, FAKE)
     assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE, FAKE,
                           1 << 40, None) == -8
-    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, FAKE, FAKE,
-                            1 << 40, None) == -8
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, FAKE, None, None,
+                            None, None, FAKE, 1 << 40, None) == -8
     p.R = None
     assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                None) == -1
