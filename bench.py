@@ -16,6 +16,8 @@ from __future__ import annotations
 import argparse
 import json
 import os
+
+import numpy as np
 import platform
 import sys
 import time
@@ -138,9 +140,15 @@ def main():
                     help="storage type of inputs and outputs (arithmetic is FP64 in both)")
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=8192)
+    ap.add_argument("--cpu-sample-steps", type=int, default=2048,
+                    help="steps of the autograd-oracle sample (the C oracle runs the whole track)")
     ap.add_argument("--cpu-sample-ct", type=int, default=64,
                     help="tracks of the coordinated-turn CPU-baseline sample")
+    ap.add_argument("--cpu-reps", type=int, default=5,
+                    help="timed runs of each C-oracle baseline (median reported)")
+    ap.add_argument("--cpu-batched-segs", type=int, default=1024,
+                    help="segments of the batched one-thread C-oracle baseline (the thread-pool "
+                         "run takes all 4096); 0: all")
     ap.add_argument("--cpu-sample-tf", type=int, default=2 ** 20,
                     help="steps of the two-filter CPU-baseline sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
@@ -157,8 +165,6 @@ def main():
                     help="skip the coordinated-turn (iterated nonlinear) measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched ragged-segment measurement (4096 segments)")
-    ap.add_argument("--cpu-sample-segs", type=int, default=1024,
-                    help="segments of the batched CPU-baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -325,41 +331,80 @@ def main():
         bt_res, wl_bt = measure_batched(args, ms, _lib, lib, timed)
         res["batched"] = bt_res
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+        import tempfile
+
+        from oracle import cref
+        native = cref.native_lib(tempfile.mkdtemp(prefix="mapscan_oracle_"))
+        res["cpu_baseline"] = cpu_baseline(wl, native, res["value"], res["plain_scan"]["value"],
+                                           args.cpu_sample_steps, args.cpu_reps)
         if two_filter is not None:
             two_filter["cpu_baseline"] = cpu_baseline_two_filter(wl, args.cpu_sample_tf)
         if ct_res is not None:
-            ct_res["cpu_baseline"] = cpu_baseline_ct(wl_ct, args.cpu_sample_ct)
+            ct_res["cpu_baseline"] = cpu_baseline_ct(wl_ct, args.cpu_sample_ct, native)
         if ex_res is not None:
-            ex_res["cpu_baseline"] = cpu_baseline_exact(wl_ex, args.cpu_sample_tf)
+            ex_res["cpu_baseline"] = cpu_baseline_exact(wl_ex, args.cpu_sample_tf, native)
         if bt_res is not None:
-            bt_res["cpu_baseline"] = cpu_baseline_batched(wl_bt, args.cpu_sample_segs)
+            bt_res["cpu_baseline"] = cpu_baseline_batched(wl_bt, native, bt_res["value"],
+                                                          args.cpu_batched_segs,
+                                                          min(args.cpu_reps, 3))
     print(json.dumps(res))
 
 
-def cpu_baseline(wl, n):
-    """The sequential oracle (PyTorch FP64 per-step loop, gradients by autograd)
-    on the first n steps of the same trajectory, one thread."""
+def host_threads():
+    """Threads for a CPU-baseline pool: the host CPUs this process may run on,
+    capped at 16 (one GPU's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def timed_runs(fn, reps=5):
+    """One untimed warm-up, then `reps` timed runs: (median, mean, all) seconds."""
+    import statistics
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), sum(ts) / len(ts), ts
+
+
+def cpu_baseline(wl, native, gpu_fa, gpu_plain, n_autograd, reps=5):
+    """The sequential C oracle, compiled for this host (gcc -O3 -march=native),
+    over the whole workload (all T steps): covariance-form Kalman filter + RTS
+    smoother with covariances + log-likelihood + objective, FP64, one thread;
+    median of 5 timed runs after one warm-up.  It computes no gradients, so the
+    fwd+adjoint speedup compares more GPU work with less CPU work.  Beside it,
+    the PyTorch oracle with its gradients by autograd on a prefix."""
     import torch
 
-    from oracle import ref
-    import workloads
+    from oracle import cref, ref
 
+    T = int(wl.n_steps)
+    med, mean, ts = timed_runs(lambda: cref.smooth(wl, lib=native), reps)
+    value = T / med
     torch.set_num_threads(1)
-    sub = workloads.Workload(**{**wl.__dict__})
-    sub.seg_off = wl.seg_off.copy()
-    sub.seg_off[-1] = n
-    sub.dt = wl.dt[:n]
-    sub.y = wl.y[:, :n]
+    sub = workloads_prefix(wl, n_autograd)
     seg = ref.workload_segment(sub, 0)
     t0 = time.perf_counter()
-    ref.gradients("cv", 4, seg, torch.zeros(n + 1, 4, dtype=torch.float64))
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d steps of the same trajectory: sequential Kalman filter + RTS "
-                      "smoother + log-likelihood + objective, gradients by autograd, FP64, "
-                      "%.1f s" % (n, dt),
-            "cpu": cpu_info()}
+    ref.gradients("cv", 4, seg, torch.zeros(n_autograd + 1, 4, dtype=torch.float64))
+    t_ag = time.perf_counter() - t0
+    return {"value": value, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "all %d steps of the workload: sequential C Kalman filter + RTS smoother + "
+                      "log-likelihood + objective (no gradients), FP64, gcc -O3 -march=native, "
+                      "median of %d runs after a warm-up (%.2f s each)" % (T, reps, med),
+            "median_s": round(med, 4), "mean_s": round(mean, 4),
+            "runs_s": [round(t, 4) for t in ts],
+            "speedup_fwd_adjoint": round(gpu_fa / value, 1),
+            "speedup_plain_scan": round(gpu_plain / value, 1),
+            "nproc": os.cpu_count(), "cpu": cpu_info(),
+            "autograd_oracle": {"value": n_autograd / t_ag, "unit": "time-steps/s", "cores": 1,
+                                "sample": "first %d steps: PyTorch per-step Kalman filter + RTS + "
+                                          "log-likelihood + objective with gradients by autograd, "
+                                          "%.1f s" % (n_autograd, t_ag)}}
 
 
 def measure_ct(args, ms, _lib, lib, timed, tdt, s):
@@ -450,34 +495,52 @@ def measure_batched(args, ms, _lib, lib, timed):
     return res, wl
 
 
-def cpu_baseline_batched(wl, n_segs):
-    """The plain-C sequential oracle (covariance Kalman filter + RTS smoother +
-    likelihood + objective, no gradients) on the first n_segs segments, one
-    thread."""
+def cpu_baseline_batched(wl, native, gpu_value, n_segs=1024, reps=3):
+    """The sequential C oracle (gcc -O3 -march=native; covariance Kalman
+    filter + RTS smoother + likelihood + objective, no gradients): one thread
+    on the first n_segs segments, and a thread pool over contiguous groups of
+    all segments on the host's threads (the C call releases the interpreter
+    lock); median of `reps` runs after a warm-up each."""
+    import concurrent.futures as cf
+
     from oracle import cref
 
-    sub = first_segments(wl, n_segs)
-    t0 = time.perf_counter()
-    cref.smooth(sub)
-    dt = time.perf_counter() - t0
-    n = int(sub.n_steps)
-    return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of the 4096 segments (%d steps): sequential C Kalman filter + "
-                      "RTS smoother + log-likelihood + objective (no gradients), FP64, %.1f s"
-                      % (n_segs, n, dt), "cpu": cpu_info()}
+    one = segment_range(wl, 0, n_segs) if 0 < n_segs < wl.n_seg else wl
+    n1 = int(one.n_steps)
+    med1, mean1, _ = timed_runs(lambda: cref.smooth(one, lib=native), reps)
+    nt = host_threads()
+    bounds = np.linspace(0, wl.n_seg, 4 * nt + 1).astype(int)
+    parts = [segment_range(wl, a, b) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    n = int(wl.n_steps)
+    with cf.ThreadPoolExecutor(nt) as ex:
+        medp, meanp, _ = timed_runs(lambda: list(ex.map(lambda w: cref.smooth(w, lib=native),
+                                                        parts)), reps)
+    return {"value": n1 / med1, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d segments (%d steps): sequential C Kalman filter + RTS "
+                      "smoother + log-likelihood + objective (no gradients), FP64, gcc -O3 "
+                      "-march=native, median of %d runs (%.2f s)"
+                      % (one.n_seg, wl.n_seg, n1, reps, med1),
+            "median_s": round(med1, 4), "mean_s": round(mean1, 4),
+            "speedup": round(gpu_value / (n1 / med1), 1),
+            "all_cores": {"value": n / medp, "unit": "time-steps/s", "cores": nt,
+                          "median_s": round(medp, 4), "mean_s": round(meanp, 4),
+                          "speedup": round(gpu_value / (n / medp), 1),
+                          "sample": "all %d segments (%d steps) in %d groups over %d threads"
+                                    % (wl.n_seg, n, len(parts), nt)},
+            "nproc": os.cpu_count(), "cpu": cpu_info()}
 
 
-def first_segments(wl, n):
-    """The first n segments of a batched workload (any lengths)."""
+def segment_range(wl, a, b):
+    """Segments a..b-1 of a batched workload as a workload of their own."""
     import workloads
 
-    k = int(wl.seg_off[n])
+    k0, k1 = int(wl.seg_off[a]), int(wl.seg_off[b])
     sub = workloads.Workload(**{**wl.__dict__})
-    sub.seg_off = wl.seg_off[:n + 1].copy()
-    sub.dt = wl.dt[:k] if len(wl.dt) > 1 else wl.dt
-    sub.y = wl.y[:, :k]
-    sub.theta, sub.m0, sub.P0 = wl.theta[:n], wl.m0[:n], wl.P0[:n]
-    sub.x_true = wl.x_true[:, :k + n]
+    sub.seg_off = wl.seg_off[a:b + 1] - k0
+    sub.dt = wl.dt[k0:k1] if len(wl.dt) > 1 else wl.dt
+    sub.y = wl.y[:, k0:k1]
+    sub.theta, sub.m0, sub.P0 = wl.theta[a:b], wl.m0[a:b], wl.P0[a:b]
+    sub.x_true = wl.x_true[:, k0 + a:k1 + b]
     return sub
 
 
@@ -537,7 +600,7 @@ def measure_exact(args, ms, _lib, lib, timed, tdt, s, wl):
     return res, wx
 
 
-def cpu_baseline_exact(wx, n):
+def cpu_baseline_exact(wx, n, native):
     """The plain-C sequential oracle (covariance Kalman filter + RTS smoother +
     likelihood + objective) on the oracle's own exact terms, first n steps."""
     import numpy as np
@@ -550,13 +613,11 @@ def cpu_baseline_exact(wx, n):
     per = lambda m: np.broadcast_to(m, (n,) + m.shape)
     sub.lin = dict(F=per(Ft), c=per(ct), L=Lt, W=Wt, H=per(wx.lin["H"]), r=per(wx.lin["r"]),
                    R=wx.lin["R"])
-    t0 = time.perf_counter()
-    cref.smooth(sub)
-    dt_ = time.perf_counter() - t0
+    dt_, _, _ = timed_runs(lambda: cref.smooth(sub, lib=native), reps=3)
     return {"value": n / dt_, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
             "sample": "first %d steps of the same track: sequential C Kalman filter + RTS "
-                      "smoother + log-likelihood + objective on exact terms, FP64, %.1f s"
-                      % (n, dt_), "cpu": cpu_info()}
+                      "smoother + log-likelihood + objective on exact terms, FP64, gcc -O3 "
+                      "-march=native, median of 3 runs (%.2f s)" % (n, dt_), "cpu": cpu_info()}
 
 
 def first_tracks(wl, n):
@@ -572,7 +633,7 @@ def first_tracks(wl, n):
     return sub
 
 
-def cpu_baseline_ct(wl, n_tracks):
+def cpu_baseline_ct(wl, n_tracks, native):
     """The plain-C sequential oracle (covariance Kalman filter + RTS per
     iteration) running the same 5 iterations on the first n_tracks tracks,
     one thread."""
@@ -580,13 +641,13 @@ def cpu_baseline_ct(wl, n_tracks):
 
     sub = first_tracks(wl, n_tracks)
     t0 = time.perf_counter()
-    cref.iterate(sub)
+    cref.iterate(sub, lib=native)
     dt = time.perf_counter() - t0
     n = int(sub.n_steps)
     return {"value": n / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
             "sample": "first %d of the 64 tracks (%d steps), 5 iterations of the sequential C "
-                      "Kalman filter + RTS smoother, FP64, %.1f s" % (n_tracks, n, dt),
-            "cpu": cpu_info()}
+                      "Kalman filter + RTS smoother, FP64, gcc -O3 -march=native, %.1f s"
+                      % (n_tracks, n, dt), "cpu": cpu_info()}
 
 
 def cpu_baseline_two_filter(wl, n):

@@ -42,6 +42,20 @@ def _load():
     return _lib
 
 
+def native_lib(out_dir: str):
+    """The same oracle compiled for the host it runs on (gcc -O3
+    -march=native, no fast-math: the arithmetic is the same IEEE arithmetic)
+    into `out_dir`, for timing it as a CPU baseline.  Returns the loaded
+    library, to pass as `lib=` to `smooth` / `iterate`."""
+    os.makedirs(out_dir, exist_ok=True)
+    so = os.path.join(out_dir, "libkfs_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-D_DEFAULT_SOURCE",
+                           "-shared", "-fPIC", os.path.join(_HERE, "kfs.c"), "-lm", "-o", so])
+    lib = ctypes.CDLL(so)
+    lib.oracle_smooth.restype = ctypes.c_long
+    return lib
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -81,9 +95,9 @@ def _terms(wl, xbar):
                 W=(Wm, 0, nw * nw), H=(H, ny * nx, 0), r=(r, ny, 0), R=(R, 0, ny * ny))
 
 
-def smooth(wl, xbar=None):
+def smooth(wl, xbar=None, lib=None):
     """Returns dict(m [n_states,nx], P [n_states,nx,nx], xs, Ps, loglik [n_seg], mstar [n_seg])."""
-    lib = _load()
+    lib = lib or _load()
     nx, ny, nw = wl.nx, wl.ny, wl.nw
     S = wl.n_seg
     NS = wl.n_states
@@ -117,7 +131,7 @@ def smooth(wl, xbar=None):
     return dict(m=m, P=P, xs=xs, Ps=Ps, loglik=ll, mstar=ms)
 
 
-def iterate(wl, n_iter=None, xbar0=None, keep_iterates=False):
+def iterate(wl, n_iter=None, xbar0=None, keep_iterates=False, lib=None):
     """Iterated linearisation (Sec. 4.4) from xbar^(0) = m0 at every state.
     Returns the last solve's outputs (with 'xbar' = its linearisation point)
     and optionally every iterate [n_iter, nx, n_states]."""
@@ -131,7 +145,7 @@ def iterate(wl, n_iter=None, xbar0=None, keep_iterates=False):
     its = []
     out = None
     for _ in range(n_iter):
-        out = smooth(wl, xbar)
+        out = smooth(wl, xbar, lib=lib)
         out["xbar"] = xbar
         xbar = out["xs"].T.copy()
         if keep_iterates:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_bench_json_contract():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1",
            "--cpu-sample-steps", "256", "--cpu-sample-ct", "1", "--cpu-sample-tf", "4096",
-           "--cpu-sample-segs", "4"]
+           "--cpu-reps", "1", "--cpu-batched-segs", "64"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=110, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     line = r.stdout.strip().splitlines()[-1]
@@ -35,6 +35,8 @@ def test_bench_json_contract():
     assert rf["unit"] == ("GB/s" if rf["bound"] == "hbm" else "TFLOP/s")
     cb = b["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+    assert cb["speedup_fwd_adjoint"] > 0 and cb["speedup_plain_scan"] > 0
+    assert b["batched"]["cpu_baseline"]["all_cores"]["cores"] >= 1
     for k in ("two_filter", "exact_dynamics", "coordinated_turn", "batched"):
         o = b[k]
         assert o["ms_per_step"] > 0 and o["value"] > 0 and "roofline" in o, k
