@@ -54,6 +54,14 @@ def library_source_hash():
     return h.hexdigest()[:16]
 
 
+def schedule_info(chunk, tuned):
+    """The schedule a run used: a flat one (states per lane) or the
+    segment-local one (one wavefront per segment)."""
+    if chunk > 0:
+        return {"kind": "flat", "states_per_lane": chunk, "autotuned": tuned}
+    return {"kind": "wavefront per segment", "states_per_lane": None, "autotuned": tuned}
+
+
 def counter_record(dtype, workload="cv4_T2p20"):
     """Per-launch counter figures of the scan kernels on a workload
     (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a device-copy calibration,
@@ -79,6 +87,8 @@ def kernel_bytes(nx, ny, s, kind):
         "traj_down_adjoint": (sym + nx + ny + nx + sym) * s,
         "two_filter_up": (ny + sym + nx) * s,             # read y, write S, v
         "two_filter_down": (sym + nx + ny + nx + sym) * s,  # read S, v, y; write xs, Ps
+        # segment-local schedule: the whole step in one kernel
+        "seg_wave": (ny + 2 * (sym + nx) + nx + sym) * s,
     }[kind]
 
 
@@ -295,7 +305,7 @@ def main():
                                "r=0.05, one trajectory; filter + smoother (x*, P^s) + log-lik + "
                                "objective + adjoint d/d(gamma,q,r)" % args.log2T,
                    "T": T, "nx": 4, "ny": 2, "n_seg": 1, "storage": args.dtype,
-                   "schedule": {"states_per_lane": chunk, "autotuned": tuned}},
+                   "schedule": schedule_info(chunk, tuned)},
         "plain_scan": {"value": T / (ms_pl * 1e-3), "ms_per_step": ms_pl,
                        "kernels_ms": {k: round(v[1], 4) for k, v in kern_pl.items()}},
         "wall_ms_per_step": round(wall_fa, 4),
@@ -446,8 +456,8 @@ def measure_ct(args, ms, _lib, lib, timed, tdt, s):
                        "2^14 steps dt=1e-3, 5 Gauss-Newton iterations from m0; x*, P^s, "
                        "log-likelihood, objective of the last",
            "n_iter": wl.n_iter, "n_steps": wl.n_steps,
-           "schedule": {"states_per_lane": ms.schedule(p),
-                        "autotuned": not args.no_autotune and args.ct_chunk == 0},
+           "schedule": schedule_info(ms.schedule(p),
+                                     not args.no_autotune and args.ct_chunk == 0),
            "roofline": roof}
     return res, wl
 
@@ -489,7 +499,7 @@ def measure_batched(args, ms, _lib, lib, timed):
                        "dt=1e-3, FP32 storage; per-segment x*, P^s, log-likelihood, objective "
                        "and adjoint d/d(gamma,q,r)" % wl.n_steps,
            "n_seg": int(n), "n_steps": int(wl.n_steps), "storage": "f32",
-           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "schedule": schedule_info(ms.schedule(p), not args.no_autotune),
            "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, 4, "f32",
                                      ms.schedule(p))}
     return res, wl
@@ -594,7 +604,7 @@ def measure_exact(args, ms, _lib, lib, timed, tdt, s, wl):
            "workload": "the same 2-D constant-velocity track (T=2^20, dt=1e-3) with exact "
                        "(matrix-exponential) dynamics in the elements, general linear model "
                        "nx=4 ny=2 nw=4; x*, P^s, log-likelihood, objective",
-           "schedule": {"states_per_lane": ms.schedule(p), "autotuned": not args.no_autotune},
+           "schedule": schedule_info(ms.schedule(p), not args.no_autotune),
            "roofline": roofline_for(kern, rec, fresh, p.n_states, p.nx, p.ny, s, args.dtype,
                                      ms.schedule(p))}
     return res, wx

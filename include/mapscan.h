@@ -69,6 +69,8 @@ extern "C" {
 #define MAPSCAN_ABI_VERSION 6
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
+/* map_problem.chunk: the segment-local schedule of map_smooth (see there) */
+#define MAP_SCHED_SEGMENT_WAVE (-1)
 
 typedef enum {
   MAP_OK = 0,
@@ -143,12 +145,17 @@ typedef struct {
    * step k at base + k * stride (stride 0: one matrix for all steps). */
   const void *F, *c, *L, *W, *H, *r, *R;
   int64_t F_stride, c_stride, L_stride, W_stride, H_stride, r_stride, R_stride;
-  /* Schedule: states per lane (4, 8, 16 or 32), or 0 to let the library
-   * choose: the choice map_autotune recorded for this problem's shape, else
-   * 32 when the filter pass then still gives every SIMD of the device four
-   * wavefronts, else the largest of 16, 8 and 4 that gives every second SIMD
-   * a wavefront.  At 32 the filter up-sweep runs 32 states per lane and the
-   * passes after it 16.
+  /* Schedule.  Flat schedules cut the concatenated states of all segments
+   * into lanes of `chunk` states (4, 8, 16 or 32; at 32 the filter up-sweep
+   * runs 32 states per lane and the passes after it 16) joined by
+   * cross-block scans.  MAP_SCHED_SEGMENT_WAVE (map_smooth and
+   * map_smooth_noalloc only; the other entry points use the flat default
+   * instead): one persistent wavefront per segment, segments taken longest
+   * first, no cross-block step (for batches of many segments).  0 lets the
+   * library choose: the choice map_autotune recorded for this problem's
+   * shape, else 32 when the filter pass then still gives every SIMD of the
+   * device four wavefronts, else the largest of 16, 8 and 4 that gives every
+   * second SIMD a wavefront.
    * Results do not depend on it beyond rounding. */
   int32_t chunk;
   /* MAP_CHECK_FINITE: the kernels flag any non-finite value they write (S, v,
@@ -281,10 +288,10 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
                         double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
                         void* vmu, double* g_xs_theta, void* ws, size_t ws_bytes, void* stream);
 
-/* Schedule autotuner for the batched segmented scan (spec item: tile
- * size per problem shape).  Times the fused step (map_smooth with every
- * output, gradients for parametric models) at chunk = 16, 8 and 4 on the
- * caller's inputs (p->chunk is ignored; p->xbar must be set for nonlinear
+/* Schedule autotuner for the batched segmented scan.  Times the fused step
+ * (map_smooth with every output, gradients for parametric models) at the
+ * flat schedules chunk = 32, 16, 8 and 4 and, for 64 or more segments, the
+ * segment-local MAP_SCHED_SEGMENT_WAVE, on the caller's inputs (p->chunk is ignored; p->xbar must be set for nonlinear
  * models) and records the fastest for this shape -- model, dimensions,
  * dtype, floor(log2 n_states), floor(log2 n_seg) -- so that later calls with
  * chunk = 0 use it.  ws: a workspace of map_workspace_bytes(p with chunk 0)
@@ -330,7 +337,7 @@ map_status map_schedule(const map_problem* p, int32_t* chunk_out);
  * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing), 7 filter
  * fix-up + backward-filter up-sweep (two-filter), 8 two-filter combination,
  * 9 the adjoint problem's passes (implicit-function VJP), 10 its per-step
- * cotangent reduction. */
+ * cotangent reduction, 11 the segment-local fused step. */
 map_status map_profile_enable(int32_t capacity);
 map_status map_profile_reset(void);
 map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms);

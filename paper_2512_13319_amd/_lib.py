@@ -21,7 +21,8 @@ EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "m
            "map_last_error", "map_abi_version"]
 PROF_KINDS = {"filter_up": 0, "filter_down": 1, "fused_down": 2, "traj_up": 3, "traj_down": 4,
               "traj_down_adjoint": 5, "aux": 6, "two_filter_up": 7, "two_filter_down": 8,
-              "ift_solve": 9, "ift_grad": 10}
+              "ift_solve": 9, "ift_grad": 10, "seg_wave": 11}
+MAP_SCHED_SEGMENT_WAVE = -1
 
 
 class MapProblem(ctypes.Structure):

@@ -14,6 +14,8 @@ constexpr int kArriveStride = 32;  // words
 constexpr int kCountersFilter = 0, kCountersTraj = kArriveWords * kArriveStride;
 // the numeric status word (MAP_CHECK_FINITE) on a line of its own after them
 constexpr int kStatusWord = 2 * kArriveWords * kArriveStride;
-constexpr int kCounterWords = kStatusWord + kArriveStride;
+// the segment queue of the segment-local schedule (reset by its order kernel)
+constexpr int kQueueWord = kStatusWord + kArriveStride;
+constexpr int kCounterWords = kQueueWord + kArriveStride;
 
 }  // namespace ms

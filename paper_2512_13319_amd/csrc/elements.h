@@ -332,6 +332,57 @@ MS_DEV void info_step(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>
   }
 }
 
+// Trajectory element (G, beta, Lam) of a state with filter (S, v) from the
+// fresh element f of the step after it: the trajectory half of info_step,
+// with its own factor Z = I + V^T S V.
+template <typename T, int N, int NW>
+MS_DEV void traj_map(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>& f,
+                     T (&G)[N][N], T (&beta)[N], T (&Lam)[N][N]) {
+  T W[N][NW];
+  mm(S, f.V, W);
+  T Z[NW][NW];
+  mtm_sym(f.V, W, Z);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) Z[i][i] += T(1);
+  T Lz[NW][NW], dz[NW];
+  chol(Z, Lz, dz);
+  T X[NW][N];
+  mtm(W, f.A, X);
+  trsm_lower(Lz, dz, X);
+  trsm_upper_t(Lz, dz, X);
+  T VX[N][N];
+  mm(f.V, X, VX);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) G[i][j] = f.A[i][j] - VX[i][j];
+  T bc[N];
+  {
+    T z[NW];
+    mtv(f.V, v, z);
+    mv(f.V, z, bc);
+#pragma unroll
+    for (int i = 0; i < N; ++i) bc[i] += f.b[i];
+  }
+  {
+    T z[NW];
+    mtv(W, bc, z);
+    trsv_lower(Lz, dz, z);
+    trsv_upper_t(Lz, dz, z);
+    T vz[N];
+    mv(f.V, z, vz);
+#pragma unroll
+    for (int i = 0; i < N; ++i) beta[i] = bc[i] - vz[i];
+  }
+  T Yv[NW][N];
+#pragma unroll
+  for (int i = 0; i < NW; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Yv[i][j] = f.V[j][i];
+  trsm_lower(Lz, dz, Yv);
+  mtm_sym(Yv, Yv, Lam);
+}
+
 // Carry application (S, v) . agg for a general run agg: only (J, eta) of the
 // result are needed.  S = 0 (no information yet) is allowed.
 template <typename T, int N>

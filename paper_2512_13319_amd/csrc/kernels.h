@@ -1652,6 +1652,194 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
 }
 
 // --------------------------------------------------------------------------- pass C
+// One state of the trajectory walk (Sec. 4.3, eq. 42), shared by the flat and
+// the segment-local schedules.  (S, v) is the filter at state i, rc the
+// fetched inputs of state i + 1; (x, P) hold the value at state i + 1 (not
+// read when i ends its segment) and receive the value at state i.  With
+// want_obj / kGrad, the objective term of the step ending at i + 1
+// (costate form) and its Fisher-identity and envelope cotangents are added
+// to val = (objective, d loglik / d theta, d obj / d theta).
+template <typename TS, typename T, class M, bool kGrad>
+MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, int64_t i,
+                                const T (&S)[M::NX][M::NX], const T (&v)[M::NX],
+                                const typename Cursor<TS, T, M>::Raw& rc, bool want_obj,
+                                T (&x)[M::NX], T (&P)[M::NX][M::NX],
+                                double (&val)[1 + 2 * (M::NTH > 0 ? M::NTH : 1)]) {
+  constexpr int N = M::NX, NY = M::NY, NW = M::NW;
+  constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
+  (void)NTH;
+  if (cur.is_last(i)) {
+    spd_inv(S, P);
+    mv(P, v, x);
+  } else {
+    Step<T, N, NY, NW> st;
+    T y[NY];
+    rc.meas(y);
+    cur.terms(p, i + 1, rc, st);
+    Fresh<T, N, NW> f;
+    fresh_from_step(st, y, f);
+    cur.ift_fresh(rc, f);
+    // trajectory map of state i (shares Z with the information step)
+    T W[N][NW];
+    mm(S, f.V, W);
+    T Z[NW][NW];
+    mtm_sym(f.V, W, Z);
+#pragma unroll
+    for (int a = 0; a < NW; ++a) Z[a][a] += T(1);
+    T Lz[NW][NW], dz[NW];
+    chol(Z, Lz, dz);
+    T X[NW][N];
+    mtm(W, f.A, X);
+    trsm_lower(Lz, dz, X);
+    trsm_upper_t(Lz, dz, X);
+    T G[N][N], VX[N][N];
+    mm(f.V, X, VX);
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) G[a][b] = f.A[a][b] - VX[a][b];
+    T bc[N], beta[N];
+    {
+      T z[NW];
+      mtv(f.V, v, z);
+      mv(f.V, z, bc);
+#pragma unroll
+      for (int a = 0; a < N; ++a) bc[a] += f.b[a];
+      mtv(W, bc, z);
+      trsv_lower(Lz, dz, z);
+      trsv_upper_t(Lz, dz, z);
+      T vz[N];
+      mv(f.V, z, vz);
+#pragma unroll
+      for (int a = 0; a < N; ++a) beta[a] = bc[a] - vz[a];
+    }
+    T Yv[NW][N], Lam[N][N];
+#pragma unroll
+    for (int a = 0; a < NW; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) Yv[a][b] = f.V[b][a];
+    trsm_lower(Lz, dz, Yv);
+    mtm_sym(Yv, Yv, Lam);
+    // x, P currently hold state i+1
+    T xn[N], Pn[N][N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) xn[a] = x[a];
+    mcopy(P, Pn);
+    traj_step(G, beta, Lam, x, P);
+    if (want_obj || kGrad) {
+      // costate lambda = v_i - S_i x*_i
+      T Sx[N], lam[N];
+      mv(S, x, Sx);
+#pragma unroll
+      for (int a = 0; a < N; ++a) lam[a] = v[a] - Sx[a];
+      T vl[NW];
+      mtv(f.V, lam, vl);
+      double ob = 0.0;
+#pragma unroll
+      for (int a = 0; a < NW; ++a) ob += 0.5 * double(vl[a]) * double(vl[a]);
+      // measurement of state i+1
+      T Hx[NY], eps[NY];
+      mv(st.H, xn, Hx);
+#pragma unroll
+      for (int a = 0; a < NY; ++a) eps[a] = y[a] - st.r[a] - Hx[a];
+      T Re[NY];
+      mv(st.Rinv, eps, Re);
+#pragma unroll
+      for (int a = 0; a < NY; ++a) ob += 0.5 * double(st.dt) * double(eps[a]) * double(Re[a]);
+      val[0] += ob;
+      if constexpr (kGrad && M::NTH > 0) {
+        // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T
+        T Yw[NW][N], Nm[N][N];
+#pragma unroll
+        for (int a = 0; a < NW; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b) Yw[a][b] = W[b][a];
+        trsm_lower(Lz, dz, Yw);
+        mtm_sym(Yw, Yw, Nm);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+          for (int b = 0; b < N; ++b) Nm[a][b] = S[a][b] - Nm[a][b];
+        T NA[N][N], NAP[N][N], E2[N][N];
+        mm(Nm, f.A, NA);
+        mm(NA, Pn, NAP);
+        mmt_sym(NAP, NA, E2);  // Nm A P^s A^T Nm
+        T Ainv[N][N];
+        inv(f.A, Ainv);
+        T GAl[N][N], GAm[N][N], GCl[N][N], GCm[N][N], Gbl[N], Gbm[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          Gbl[a] = lam[a];
+          Gbm[a] = -lam[a];
+#pragma unroll
+          for (int b = 0; b < N; ++b) {
+            const T lx = lam[a] * xn[b];
+            GAl[a][b] = lx - NAP[a][b] + Ainv[b][a];
+            GAm[a][b] = -lx;
+            const T ll_ = lam[a] * lam[b];
+            GCl[a][b] = T(0.5) * (ll_ + E2[a][b] - Nm[a][b]);
+            GCm[a][b] = T(-0.5) * ll_;
+          }
+        }
+        // measurement: R-cotangents
+        T HP[NY][N], HPH[NY][NY];
+        mm(st.H, Pn, HP);
+        mmt_sym(HP, st.H, HPH);
+        T GRl[NY][NY], GRm[NY][NY];
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+#pragma unroll
+          for (int b = 0; b < NY; ++b) {
+            T sRe = Re[a] * Re[b];
+            T t2[1];
+            t2[0] = T(0);
+#pragma unroll
+            for (int c = 0; c < NY; ++c)
+#pragma unroll
+              for (int d = 0; d < NY; ++d) t2[0] += st.Rinv[a][c] * HPH[c][d] * st.Rinv[d][b];
+            GRl[a][b] = T(-0.5) * st.Rinv[a][b] + T(0.5) * st.dt * (sRe + t2[0]);
+            GRm[a][b] = T(-0.5) * st.dt * sRe;
+          }
+        T xb[N];
+        if constexpr (M::kNonlinear) {
+#pragma unroll
+          for (int a = 0; a < N; ++a) xb[a] = T(rc.xb[a]);
+        } else {
+#pragma unroll
+          for (int a = 0; a < N; ++a) xb[a] = T(0);
+        }
+        double gl[NTH], gm[NTH];
+#pragma unroll
+        for (int t = 0; t < NTH; ++t) gl[t] = gm[t] = 0.0;
+        M::vjp(cur.th, xb, st.dt, GAl, Gbl, GCl, GRl, gl);
+        M::vjp(cur.th, xb, st.dt, GAm, Gbm, GCm, GRm, gm);
+#pragma unroll
+        for (int t = 0; t < NTH; ++t) {
+          val[1 + t] += gl[t];
+          val[1 + NTH + t] += gm[t];
+        }
+      }
+    }
+  }
+}
+
+// Prior term 1/2 |x_0 - m0|^2_{P0^{-1}} of the objective at a segment's first state.
+template <typename TS, typename T, class M>
+MS_DEVONLY double prior_objective(const Prob<TS>& p, const Cursor<TS, T, M>& cur,
+                                  const T (&x)[M::NX]) {
+  constexpr int N = M::NX;
+  T S0[N][N], v0[N], m0[N], P0i[N][N];
+  cur.prior(p, S0, v0, m0, P0i);
+  T dlt[N], Pd[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) dlt[a] = x[a] - m0[a];
+  mv(P0i, dlt, Pd);
+  double ob = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) ob += 0.5 * double(dlt[a]) * double(Pd[a]);
+  return ob;
+}
+
 struct TrajOut {
   const void* S;
   const void* v;
@@ -1741,175 +1929,12 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       vec_from_raw(q.v, v);
       filter_plane_in<TS>(S, v);
       const typename Cursor<TS, T, M>::Raw rc = q.r;
-      if (cur.is_last(i)) {
-        spd_inv(S, P);
-        mv(P, v, x);
-      } else {
-        Step<T, N, NY, NW> st;
-        T y[NY];
-        rc.meas(y);
-        cur.terms(p, i + 1, rc, st);
-        Fresh<T, N, NW> f;
-        fresh_from_step(st, y, f);
-        cur.ift_fresh(rc, f);
-        // trajectory map of state i (shares Z with the information step)
-        T W[N][NW];
-        mm(S, f.V, W);
-        T Z[NW][NW];
-        mtm_sym(f.V, W, Z);
-#pragma unroll
-        for (int a = 0; a < NW; ++a) Z[a][a] += T(1);
-        T Lz[NW][NW], dz[NW];
-        chol(Z, Lz, dz);
-        T X[NW][N];
-        mtm(W, f.A, X);
-        trsm_lower(Lz, dz, X);
-        trsm_upper_t(Lz, dz, X);
-        T G[N][N], VX[N][N];
-        mm(f.V, X, VX);
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-          for (int b = 0; b < N; ++b) G[a][b] = f.A[a][b] - VX[a][b];
-        T bc[N], beta[N];
-        {
-          T z[NW];
-          mtv(f.V, v, z);
-          mv(f.V, z, bc);
-#pragma unroll
-          for (int a = 0; a < N; ++a) bc[a] += f.b[a];
-          mtv(W, bc, z);
-          trsv_lower(Lz, dz, z);
-          trsv_upper_t(Lz, dz, z);
-          T vz[N];
-          mv(f.V, z, vz);
-#pragma unroll
-          for (int a = 0; a < N; ++a) beta[a] = bc[a] - vz[a];
-        }
-        T Yv[NW][N], Lam[N][N];
-#pragma unroll
-        for (int a = 0; a < NW; ++a)
-#pragma unroll
-          for (int b = 0; b < N; ++b) Yv[a][b] = f.V[b][a];
-        trsm_lower(Lz, dz, Yv);
-        mtm_sym(Yv, Yv, Lam);
-        // x, P currently hold state i+1
-        T xn[N], Pn[N][N];
-#pragma unroll
-        for (int a = 0; a < N; ++a) xn[a] = x[a];
-        mcopy(P, Pn);
-        traj_step(G, beta, Lam, x, P);
-        if (to.want_obj || kGrad) {
-          // costate lambda = v_i - S_i x*_i
-          T Sx[N], lam[N];
-          mv(S, x, Sx);
-#pragma unroll
-          for (int a = 0; a < N; ++a) lam[a] = v[a] - Sx[a];
-          T vl[NW];
-          mtv(f.V, lam, vl);
-          double ob = 0.0;
-#pragma unroll
-          for (int a = 0; a < NW; ++a) ob += 0.5 * double(vl[a]) * double(vl[a]);
-          // measurement of state i+1
-          T Hx[NY], eps[NY];
-          mv(st.H, xn, Hx);
-#pragma unroll
-          for (int a = 0; a < NY; ++a) eps[a] = y[a] - st.r[a] - Hx[a];
-          T Re[NY];
-          mv(st.Rinv, eps, Re);
-#pragma unroll
-          for (int a = 0; a < NY; ++a) ob += 0.5 * double(st.dt) * double(eps[a]) * double(Re[a]);
-          val[0] += ob;
-          if constexpr (kGrad && M::NTH > 0) {
-            // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T
-            T Yw[NW][N], Nm[N][N];
-#pragma unroll
-            for (int a = 0; a < NW; ++a)
-#pragma unroll
-              for (int b = 0; b < N; ++b) Yw[a][b] = W[b][a];
-            trsm_lower(Lz, dz, Yw);
-            mtm_sym(Yw, Yw, Nm);
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-              for (int b = 0; b < N; ++b) Nm[a][b] = S[a][b] - Nm[a][b];
-            T NA[N][N], NAP[N][N], E2[N][N];
-            mm(Nm, f.A, NA);
-            mm(NA, Pn, NAP);
-            mmt_sym(NAP, NA, E2);  // Nm A P^s A^T Nm
-            T Ainv[N][N];
-            inv(f.A, Ainv);
-            T GAl[N][N], GAm[N][N], GCl[N][N], GCm[N][N], Gbl[N], Gbm[N];
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-              Gbl[a] = lam[a];
-              Gbm[a] = -lam[a];
-#pragma unroll
-              for (int b = 0; b < N; ++b) {
-                const T lx = lam[a] * xn[b];
-                GAl[a][b] = lx - NAP[a][b] + Ainv[b][a];
-                GAm[a][b] = -lx;
-                const T ll_ = lam[a] * lam[b];
-                GCl[a][b] = T(0.5) * (ll_ + E2[a][b] - Nm[a][b]);
-                GCm[a][b] = T(-0.5) * ll_;
-              }
-            }
-            // measurement: R-cotangents
-            T HP[NY][N], HPH[NY][NY];
-            mm(st.H, Pn, HP);
-            mmt_sym(HP, st.H, HPH);
-            T GRl[NY][NY], GRm[NY][NY];
-#pragma unroll
-            for (int a = 0; a < NY; ++a)
-#pragma unroll
-              for (int b = 0; b < NY; ++b) {
-                T sRe = Re[a] * Re[b];
-                T t2[1];
-                t2[0] = T(0);
-#pragma unroll
-                for (int c = 0; c < NY; ++c)
-#pragma unroll
-                  for (int d = 0; d < NY; ++d) t2[0] += st.Rinv[a][c] * HPH[c][d] * st.Rinv[d][b];
-                GRl[a][b] = T(-0.5) * st.Rinv[a][b] + T(0.5) * st.dt * (sRe + t2[0]);
-                GRm[a][b] = T(-0.5) * st.dt * sRe;
-              }
-            T xb[N];
-            if constexpr (M::kNonlinear) {
-#pragma unroll
-              for (int a = 0; a < N; ++a) xb[a] = T(rc.xb[a]);
-            } else {
-#pragma unroll
-              for (int a = 0; a < N; ++a) xb[a] = T(0);
-            }
-            double gl[NTH], gm[NTH];
-#pragma unroll
-            for (int t = 0; t < NTH; ++t) gl[t] = gm[t] = 0.0;
-            M::vjp(cur.th, xb, st.dt, GAl, Gbl, GCl, GRl, gl);
-            M::vjp(cur.th, xb, st.dt, GAm, Gbm, GCm, GRm, gm);
-#pragma unroll
-            for (int t = 0; t < NTH; ++t) {
-              val[1 + t] += gl[t];
-              val[1 + NTH + t] += gm[t];
-            }
-          }
-        }
-      }
+      traj_walk_state<TS, T, M, kGrad>(p, cur, i, S, v, rc, to.want_obj != 0, x, P, val);
       tstore_vec(xo, N, i, x);
       if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
       if (ws.status) bad = bad | (kCov ? nonfinite_vd(x, P) : nonfinite_v(x));
       if (cur.is_head(i)) {
-        if (to.want_obj) {
-          T S0[N][N], v0[N], m0[N], P0i[N][N];
-          cur.prior(p, S0, v0, m0, P0i);
-          T dlt[N], Pd[N];
-#pragma unroll
-          for (int a = 0; a < N; ++a) dlt[a] = x[a] - m0[a];
-          mv(P0i, dlt, Pd);
-          double ob = 0.0;
-#pragma unroll
-          for (int a = 0; a < N; ++a) ob += 0.5 * double(dlt[a]) * double(Pd[a]);
-          val[0] += ob;
-        }
+        if (to.want_obj) val[0] += prior_objective(p, cur, x);
         if (i > j0) {
           flush_lane<KV>(seg_acc, val, dst, dstr);
           cur.prev(p);

@@ -8,6 +8,7 @@
 
 #include <map>
 #include <mutex>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -136,7 +137,10 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
   if (p.model < MAP_MODEL_LINEAR || p.model > MAP_MODEL_CT)
     return fail(MAP_E_ARG, "unknown model %d", p.model);
   if (p.chunk != 0 && !valid_chunk(p.chunk))
-    return fail(MAP_E_ARG, "chunk = %d; must be 0 (library's choice), 4, 8, 16 or 32", p.chunk);
+    return fail(MAP_E_ARG,
+                "chunk = %d; must be 0 (library's choice), 4, 8, 16, 32 or "
+                "MAP_SCHED_SEGMENT_WAVE (-1)",
+                p.chunk);
   if (p.flags & ~MAP_CHECK_FINITE) return fail(MAP_E_ARG, "unknown flags 0x%x", unsigned(p.flags));
   const int nth = model_ntheta(p);
   if (nth < 0)
@@ -229,27 +233,43 @@ int heuristic(const map_problem& p) {
   return kMinChunk;
 }
 
-int resolve(const map_problem& p) {
-  if (p.chunk != 0) return p.chunk;
-  {
+// The schedule of a call.  The segment-local schedule serves the fused step
+// only (map_smooth, map_smooth_noalloc, and the iterations of
+// map_iterated_nonlinear); the other entry points (allow_seg = false) use the
+// flat heuristic where it was asked for or tuned.
+int resolve(const map_problem& p, bool allow_seg) {
+  int c = p.chunk;
+  if (c == 0) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tuned.find(key_of(p));
-    if (it != g_tuned.end()) return it->second;
+    if (it != g_tuned.end()) c = it->second;
   }
-  return heuristic(p);
+  if (c == 0) c = heuristic(p);
+  if (c == kSchedSegWave && (!allow_seg || p.n_seg > int64_t(INT32_MAX))) c = heuristic(p);
+  return c;
 }
 
-// workspace that fits the schedule `resolve` may pick (every schedule when the
-// choice is left to the library)
+// workspace bytes of one schedule
+size_t ws_need(const map_problem& p, int chunk) {
+  if (chunk == kSchedSegWave) return seg_ws_bytes(p.n_seg);
+  return ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), chunk).total;
+}
+
+// workspace that fits the schedule `resolve` may pick for any entry point
+// (every schedule when the choice is left to the library)
 size_t ws_bytes_for(const map_problem& p) {
-  const int64_t ns = p.n_steps + p.n_seg;
-  if (p.chunk != 0) return ws_layout(p.nx, ns, compute_bytes(p.dtype), p.chunk).total;
   size_t m = 0;
+  if (p.chunk != 0) {
+    m = ws_need(p, resolve(p, false));
+    const size_t t = ws_need(p, resolve(p, true));
+    return t > m ? t : m;
+  }
   for (int c : kChunks) {
-    const size_t t = ws_layout(p.nx, ns, compute_bytes(p.dtype), c).total;
+    const size_t t = ws_need(p, c);
     if (t > m) m = t;
   }
-  return m;
+  const size_t t = ws_need(p, kSchedSegWave);
+  return t > m ? t : m;
 }
 }  // namespace sched
 
@@ -302,9 +322,8 @@ map_status scratch_address(void** out) {
   return MAP_OK;
 }
 
-map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes) {
-  const size_t need =
-      ws_layout(p.nx, p.n_steps + p.n_seg, compute_bytes(p.dtype), sched::resolve(p)).total;
+map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes, bool allow_seg) {
+  const size_t need = sched::ws_need(p, sched::resolve(p, allow_seg));
   if (ws == nullptr) return fail(MAP_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < need)
     return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -398,9 +417,9 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr) return fail(MAP_E_ARG, "S/v is NULL");
   if ((m == nullptr) != (P == nullptr)) return fail(MAP_E_ARG, "m and P must be given together");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
-               static_cast<hipStream_t>(stream), sched::resolve(*p)};
+               static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoFilter{*p, a}));
 }
 
@@ -409,9 +428,9 @@ map_status map_smoother_scan(const map_problem* p, const void* S, const void* v,
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               nullptr, nullptr, ws, static_cast<hipStream_t>(stream), sched::resolve(*p)};
+               nullptr, nullptr, ws, static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoSmoother{*p, a, false}));
 }
 
@@ -423,9 +442,9 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
-               static_cast<hipStream_t>(stream), sched::resolve(*p)};
+               static_cast<hipStream_t>(stream), sched::resolve(*p, true)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoSmooth{*p, a}));
 }
 
@@ -437,8 +456,8 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
-  const int chunk = sched::resolve(*p);
-  const size_t need = ws_layout(p->nx, p->n_steps + p->n_seg, compute_bytes(p->dtype), chunk).total;
+  const int chunk = sched::resolve(*p, true);
+  const size_t need = sched::ws_need(*p, chunk);
   if (need > kScratchBytes)
     return fail(MAP_E_WORKSPACE,
                 "map_smooth_noalloc: the problem needs %zu bytes of workspace, the fixed scratch "
@@ -460,9 +479,9 @@ map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* x
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
-               static_cast<hipStream_t>(stream), sched::resolve(*p)};
+               static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoTwoFilter{*p, a}));
 }
 
@@ -478,7 +497,7 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
   if (xbar_buf == xs) return fail(MAP_E_ARG, "xbar_buf must not alias xs");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t ns = p->n_steps + p->n_seg;
   const size_t tiles = size_t((ns + 1023) / 1024);
@@ -501,7 +520,7 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
     q.xbar = bufs[cur];
     SmoothArgs a{S, v, nullptr, nullptr, bufs[1 - cur], last ? Ps : nullptr,
                  last ? loglik : nullptr, last ? obj : nullptr, last ? g_loglik : nullptr,
-                 last ? g_obj : nullptr, ws, st, sched::resolve(q)};
+                 last ? g_obj : nullptr, ws, st, sched::resolve(q, true)};
     s = dispatch(q, DoSmooth{q, a});
     if (s != MAP_OK) return s;
     cur = 1 - cur;
@@ -528,10 +547,10 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
           return fail(MAP_E_ARG, "xs, mu and vmu must be distinct and not alias S, v or g_xs");
   }
   if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
-  if ((s = check_ws(*p, ws, ws_bytes)) != MAP_OK) return s;
+  if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               g_loglik, g_obj, ws, st, sched::resolve(*p)};
+               g_loglik, g_obj, ws, st, sched::resolve(*p, false)};
   s = dispatch(*p, DoSmoother{*p, a, g_loglik != nullptr || g_obj != nullptr});
   if (s == MAP_OK && g_xs != nullptr)
     s = dispatch(*p, DoIft{*p, a, IftArgs{g_xs, mu, vmu, g_xs_theta}});
@@ -599,7 +618,10 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
   int best = 0;
   float best_ms = 0.f;
   constexpr int kReps = 3;
-  for (int c : kChunks) {
+  // the flat schedules, and for batches of many segments the segment-local one
+  std::vector<int> cands(std::begin(kChunks), std::end(kChunks));
+  if (q.n_seg >= 64 && q.n_seg <= int64_t(INT32_MAX)) cands.push_back(kSchedSegWave);
+  for (int c : cands) {
     q.chunk = c;
     SmoothArgs a{buf[0], buf[1], nullptr, nullptr, buf[2], buf[3], static_cast<double*>(buf[4]),
                  static_cast<double*>(buf[5]), static_cast<double*>(buf[6]),
@@ -678,7 +700,7 @@ map_status map_schedule(const map_problem* p, int32_t* chunk_out) {
   map_status s = validate(p, false);
   if (s != MAP_OK) return s;
   if (chunk_out == nullptr) return fail(MAP_E_ARG, "chunk_out is NULL");
-  *chunk_out = sched::resolve(*p);
+  *chunk_out = sched::resolve(*p, true);
   return MAP_OK;
 }
 

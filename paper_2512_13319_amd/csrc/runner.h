@@ -29,14 +29,25 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // left its compute unit).  The storage layout of state-indexed arrays does
 // not depend on this.
 constexpr int64_t kMergeStates = 8;
-constexpr int kChunks[4] = {32, 16, 8, 4};  // schedules, largest first
+constexpr int kChunks[4] = {32, 16, 8, 4};  // flat schedules, largest first
 constexpr int kMinChunk = 4;
-inline bool valid_chunk(int c) { return c == 4 || c == 8 || c == 16 || c == 32; }
+// Segment-local schedule of the fused step (map_smooth): one wavefront per
+// segment, in rounds of 64 lanes x 16 states (segwave.h).
+constexpr int kSchedSegWave = MAP_SCHED_SEGMENT_WAVE;
+inline bool valid_flat_chunk(int c) { return c == 4 || c == 8 || c == 16 || c == 32; }
+inline bool valid_chunk(int c) { return valid_flat_chunk(c) || c == kSchedSegWave; }
 // Schedule 32 is split: the filter up-sweep folds 32 states per lane (its
 // wavefront scan, block tree and arrival then cost half as much per state)
 // and also keeps the fold of each lane's first 16; the passes after it run 16
 // per lane, which keeps their streamed accesses on whole cache lines.
 inline int later_chunk(int chunk) { return chunk == 32 ? 16 : chunk; }
+
+// Workspace of the segment-local schedule: the control words and the segment
+// queue (one int per segment).
+inline size_t seg_ws_order_offset() { return align256(size_t(kCounterWords) * 4); }
+inline size_t seg_ws_bytes(int64_t n_seg) {
+  return seg_ws_order_offset() + align256(size_t(n_seg) * sizeof(int));
+}
 
 inline int64_t work_tiles(int64_t n_states, int64_t chunk) {
   const int64_t ts = 64 * chunk;
@@ -114,7 +125,8 @@ enum ProfKind : int {
   kProfTwoFilterDown = 8,
   kProfIftSolve = 9,
   kProfIftGrad = 10,
-  kProfKinds = 11
+  kProfSegWave = 11,
+  kProfKinds = 12
 };
 void prof_begin(int kind, hipStream_t st);
 void prof_end(int kind, hipStream_t st);

@@ -2,6 +2,7 @@
 #pragma once
 #include "kernels.h"
 #include "runner.h"
+#include "segwave.h"
 
 namespace ms {
 
@@ -185,8 +186,61 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
   return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 
+// Blocks of k_seg_wave<...> resident on the whole device (its persistent grid).
+template <typename TS, typename T, class M, bool kGrad, bool kCov>
+unsigned seg_wave_grid(int64_t n_seg) {
+  static int resident = 0;
+  if (resident == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seg_wave<TS, T, M, kGrad, kCov>,
+                                                     kBlock, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    resident = per_cu * cus;
+  }
+  const int64_t want = (n_seg + kBlock / kWave - 1) / (kBlock / kWave);
+  return unsigned(want < resident ? want : resident);
+}
+
+template <typename TS, typename T, class M, bool kGrad, bool kCov>
+hipError_t launch_seg_wave(const Prob<TS>& p, const SegOut& o, hipStream_t st) {
+  prof_begin(kProfSegWave, st);
+  k_seg_wave<TS, T, M, kGrad, kCov>
+      <<<seg_wave_grid<TS, T, M, kGrad, kCov>(p.n_seg), kBlock, 0, st>>>(p, o);
+  prof_end(kProfSegWave, st);
+  return hipGetLastError();
+}
+
+// Segment-local schedule of the fused step (segwave.h): the queue of segments
+// by decreasing length, then the persistent wavefronts.
+template <typename TS, typename T, class M>
+hipError_t smooth_seg_wave(const map_problem& q, const SmoothArgs& a) {
+  Prob<TS> p = make_prob<TS>(q);
+  char* base = static_cast<char*>(a.ws);
+  unsigned int* ctl = reinterpret_cast<unsigned int*>(base);
+  int* order = reinterpret_cast<int*>(base + seg_ws_order_offset());
+  prof_begin(kProfAux, a.stream);
+  k_seg_order<<<1, kBlock, 0, a.stream>>>(q.seg_off, q.n_seg, order, ctl + kQueueWord);
+  prof_end(kProfAux, a.stream);
+  MS_CHECK(hipGetLastError());
+  const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
+  SegOut o{a.S, a.v, a.xs, a.Ps, a.loglik, a.obj, a.g_loglik, a.g_obj, order,
+           ctl + kQueueWord, (q.flags & MAP_CHECK_FINITE) ? ctl + kStatusWord : nullptr};
+  if constexpr (M::kAdjoint) {
+    if (grad)
+      return a.Ps ? launch_seg_wave<TS, T, M, true, true>(p, o, a.stream)
+                  : launch_seg_wave<TS, T, M, true, false>(p, o, a.stream);
+  }
+  return a.Ps ? launch_seg_wave<TS, T, M, false, true>(p, o, a.stream)
+              : launch_seg_wave<TS, T, M, false, false>(p, o, a.stream);
+}
+
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
+  if (a.chunk == kSchedSegWave) return smooth_seg_wave<TS, T, M>(q, a);
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;

@@ -85,11 +85,18 @@ def test_linear_smoother_parity(case, dtype):
     _check_linear(case, dtype, 0)
 
 
-@pytest.mark.parametrize("chunk", [8, 16, 32])
+@pytest.mark.parametrize("chunk", [8, 16, 32, -1])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_linear_smoother_parity_schedules(case, chunk):
-    """The other work decompositions (8, 16 and 32 states per lane)."""
+    """The other work decompositions (8, 16 and 32 states per lane; -1: one
+    wavefront per segment)."""
     _check_linear(case, "f64", chunk)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_segment_wave_schedule_f32(case):
+    """The segment-local schedule with FP32 storage."""
+    _check_linear(case, "f32", -1)
 
 
 def _check_linear(case, dtype, chunk):
@@ -217,20 +224,21 @@ def test_gradients_match_oracle_autograd(model):
 
 
 def test_schedules_agree_with_gradients():
-    """Fused step with the adjoint at 4, 8, 16 and 32 states per lane: every
-    output agrees across schedules and with the oracle."""
+    """Fused step with the adjoint at 4, 8, 16 and 32 states per lane and with
+    one wavefront per segment: every output agrees across schedules and with
+    the oracle."""
     ms = _mapscan()
     wl = workloads.cv_batched(n_seg=11, lmin=5.0, lmax=11.5, seed=21)
     o = cref.smooth(wl)
     res = {}
-    for c in (4, 8, 16, 32):
+    for c in (4, 8, 16, 32, -1):
         p = ms.problem_from_workload(wl, dtype=torch.float64, chunk=c)
         r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
         torch.cuda.synchronize()
         res[c] = {k: v.double().cpu().numpy() for k, v in r.items() if v is not None}
         assert rel_err(planes_T(r["xs"]), o["xs"]) <= 1e-9
         assert np.abs(res[c]["loglik"] - o["loglik"]).max() <= 1e-9 * np.abs(o["loglik"]).max()
-    for c in (8, 16, 32):
+    for c in (8, 16, 32, -1):
         for k in ("xs", "Ps", "loglik", "obj", "g_loglik", "g_obj"):
             a, b = res[c][k], res[4][k]
             assert np.abs(a - b).max() <= 1e-10 * max(np.abs(b).max(), 1e-300), (c, k)
