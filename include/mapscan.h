@@ -69,6 +69,17 @@ extern "C" {
 #define MAPSCAN_ABI_VERSION 6
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
+/* map_problem.flags: minimise the Onsager--Machlup objective with its
+ * divergence term (Sec. 2.1, eq. OM: + 1/2 sum_k dt_k div f(x_k) in the
+ * discretised objective) instead of the energy part alone.  Where div f
+ * depends on the state (Van der Pol: mu (1 - x1^2)) each linearisation also
+ * takes the term's second-order expansion about xbar (a Newton step on it;
+ * the Gauss--Newton step of Sec. 4.4 drops it).  x*, P^s (the inverse
+ * Hessian of the expanded objective) and the objective (with the term,
+ * evaluated at x*) only: log-likelihood and gradients are rejected, as is
+ * the two-filter form.  Valid while the combined information stays positive
+ * definite (Van der Pol: 1/r > mu). */
+#define MAP_OM_DIVERGENCE 2
 /* map_problem.chunk: the segment-local schedule of map_smooth (see there) */
 #define MAP_SCHED_SEGMENT_WAVE (-1)
 
@@ -158,7 +169,8 @@ typedef struct {
    * second SIMD a wavefront.
    * Results do not depend on it beyond rounding. */
   int32_t chunk;
-  /* MAP_CHECK_FINITE: the kernels flag any non-finite value they write (S, v,
+  /* Flags: MAP_OM_DIVERGENCE (above), and
+   * MAP_CHECK_FINITE: the kernels flag any non-finite value they write (S, v,
    * x*, P^s diagonals, log-likelihood, objective, gradients); the entry point
    * then waits for its stream, and returns MAP_E_NUMERIC if one was seen (a
    * non-finite input, or a covariance that is not positive definite).  The

@@ -172,6 +172,21 @@ def drift_torch(model: str, theta: torch.Tensor, x: torch.Tensor, nx: int):
     raise ValueError(model)
 
 
+def divergence_torch(model: str, theta: torch.Tensor, x: torch.Tensor, nx: int):
+    """div f(x) = trace of the drift's Jacobian, the divergence term of the
+    Onsager--Machlup functional (Sec. 2.1, eq. OM), x [T, nx] -> [T]."""
+    T = x.shape[0]
+    if model == "cv":
+        return -(nx // 2) * theta[0] * torch.ones(T, dtype=x.dtype)
+    if model == "vdp":
+        return theta[0] * (1.0 - x[:, 0] * x[:, 0])
+    if model == "lorenz63":
+        return -(theta[0] + 1.0 + theta[2]) * torch.ones(T, dtype=x.dtype)
+    if model == "ct":
+        return torch.zeros(T, dtype=x.dtype)
+    raise ValueError(model)
+
+
 # ----------------------------------------------------------------------------- numpy
 
 def terms_numpy(model: str, theta: np.ndarray, xbar: np.ndarray, nx: int, y=None):

@@ -42,9 +42,12 @@ def _step_mats(F, c, L, W, dt):
     return Phi, Q
 
 
-def kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0):
+def kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0, dJ=None, deta=None):
     """F [T,nx,nx], c [T,nx], H [T,ny,nx], r [T,ny], dt [T], y [T,ny];
-    L, W, R shared by all steps of the segment.
+    L, W, R shared by all steps of the segment.  dJ [T,nx,nx], deta [T,nx]
+    (optional): one more quadratic cost term 1/2 x^T dJ x - x^T deta on each
+    step's right-end state, folded in after the measurement update in
+    information form (P <- (P^-1 + dJ)^-1, m <- P (P_old^-1 m_old + deta)).
     Returns m [T+1,nx], P [T+1,nx,nx], predicted mp/Pp [T,...], loglik."""
     T = y.shape[0]
     ny = y.shape[1]
@@ -63,6 +66,11 @@ def kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0):
         m = mp + K @ e
         P = Pp - K @ Sg @ K.T
         P = 0.5 * (P + P.T)
+        if dJ is not None:
+            Si = torch.linalg.inv(P)
+            P = torch.linalg.inv(Si + dJ[k])
+            P = 0.5 * (P + P.T)
+            m = P @ (Si @ m + deta[k])
         ms.append(m); Ps.append(P); mps.append(mp); Pps.append(Pp)
     return torch.stack(ms), torch.stack(Ps), torch.stack(mps), torch.stack(Pps), ll
 
@@ -123,31 +131,63 @@ def map_objective_nonlinear(model, theta, x, dt, y, m0, P0, nx):
     return M
 
 
-def smooth_segment(model, theta, xbar, dt, y, m0, P0, nx, lin=None):
+def divergence_expansion(model, theta, xbar, dt, nx):
+    """Second-order Taylor expansion about xbar [T, nx] of each step's term
+    1/2 dt_k div f(x_k) of the Onsager--Machlup objective (Sec. 2.1, eq. OM),
+    written as 1/2 x^T dJ x - x^T deta + const (the form of an element's J and
+    eta): dJ = 1/2 dt Hess, deta = -1/2 dt (grad - Hess xbar), gradient and
+    Hessian of div f by autograd."""
+    dJ, deta = [], []
+    for k in range(xbar.shape[0]):
+        xk = xbar[k].detach()
+        fn = lambda x: models.divergence_torch(model, theta.detach(), x[None], nx)[0]
+        g = torch.autograd.functional.jacobian(fn, xk)
+        Hs = torch.autograd.functional.hessian(fn, xk)
+        dJ.append(0.5 * dt[k] * Hs)
+        deta.append(-0.5 * dt[k] * (g - Hs @ xk))
+    return torch.stack(dJ), torch.stack(deta)
+
+
+def om_objective(model, theta, x, dt, y, m0, P0, nx):
+    """The discretised Onsager--Machlup objective with its divergence term:
+    map_objective_nonlinear + sum_k 1/2 dt_k div f(x_k)."""
+    div = models.divergence_torch(model, theta, x[1:], nx)
+    return map_objective_nonlinear(model, theta, x, dt, y, m0, P0, nx) + 0.5 * (dt * div).sum()
+
+
+def smooth_segment(model, theta, xbar, dt, y, m0, P0, nx, lin=None, om_div=False):
     """One linear-affine solve about xbar [T+1, nx] (states).  Returns a dict
     with filter m, P, smoother xs, Ps, loglik and mstar = M_d(xs).  For the
-    model "linear" the matrices come from `lin` (torch tensors, per step)."""
+    model "linear" the matrices come from `lin` (torch tensors, per step).
+    With om_div, the divergence term of eq. OM enters by its second-order
+    expansion about xbar (a Newton step on it), and mstar includes the term
+    at xs (loglik is then not meaningful)."""
     if lin is not None:
         F, c, L, W, H, r, R = (lin[k] for k in ("F", "c", "L", "W", "H", "r", "R"))
     else:
         F, c, L, W, H, r, R = models.terms_torch(model, theta, xbar[1:], nx, y)
-    m, P, mp, Pp, ll = kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0)
+    dJ = deta = None
+    if om_div:
+        dJ, deta = divergence_expansion(model, theta, xbar[1:], dt, nx)
+    m, P, mp, Pp, ll = kalman_filter(F, c, L, W, H, r, R, dt, y, m0, P0, dJ, deta)
     xs, Ps = rts_smoother(F, dt, m, P, mp, Pp)
     M = map_objective(xs, F, c, L, W, H, r, R, dt, y, m0, P0)
+    if om_div:
+        M = M + 0.5 * (dt * models.divergence_torch(model, theta, xs[1:], nx)).sum()
     return dict(m=m, P=P, xs=xs, Ps=Ps, loglik=ll, mstar=M)
 
 
-def gauss_newton(model, theta, dt, y, m0, P0, nx, n_iter, xbar0=None):
+def gauss_newton(model, theta, dt, y, m0, P0, nx, n_iter, xbar0=None, om_div=False):
     """Iterated linearisation (Sec. 4.4).  xbar^(0) = m0 at every state unless
     given.  Returns the list of iterates [xbar^(1), ..., xbar^(n_iter)] and the
     outputs of the last linear solve (whose linearisation point is the
-    iterate before it, held fixed)."""
+    iterate before it, held fixed).  om_div: see smooth_segment."""
     T = y.shape[0]
     xbar = m0.expand(T + 1, nx).clone() if xbar0 is None else xbar0
     its = []
     out = None
     for _ in range(n_iter):
-        out = smooth_segment(model, theta, xbar.detach(), dt, y, m0, P0, nx)
+        out = smooth_segment(model, theta, xbar.detach(), dt, y, m0, P0, nx, om_div=om_div)
         out["xbar"] = xbar.detach()
         xbar = out["xs"]
         its.append(xbar.detach())

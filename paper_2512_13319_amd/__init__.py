@@ -113,13 +113,18 @@ class Problem:
     check_finite  every call waits for its stream and raises if a non-finite
               value was written (non-finite inputs, or a covariance that is not
               positive definite)
+    om_divergence  minimise the Onsager--Machlup objective with its divergence
+              term (a Newton step on it where it depends on the state); x*,
+              P^s and the objective only (see MAP_OM_DIVERGENCE)
     """
 
     def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
-                 dtype=torch.float64, device="cuda", arith="f64", chunk=0, check_finite=False):
+                 dtype=torch.float64, device="cuda", arith="f64", chunk=0, check_finite=False,
+                 om_divergence=False):
         _lib.load()
         self.chunk = int(chunk)
         self.check_finite = bool(check_finite)
+        self.om_divergence = bool(om_divergence)
         self.model, self.nx, self.ny, self.nw = model, nx, ny, nw
         self.dtype, self.device = dtype, torch.device(device)
         if arith not in ("f64", "f32") or (arith == "f32" and dtype != torch.float32):
@@ -171,7 +176,8 @@ class Problem:
         s.n_theta = self.n_theta
         s.n_seg, s.n_steps = self.n_seg, self.n_steps
         s.chunk = self.chunk
-        s.flags = _lib.MAP_CHECK_FINITE if self.check_finite else 0
+        s.flags = ((_lib.MAP_CHECK_FINITE if self.check_finite else 0)
+                   | (_lib.MAP_OM_DIVERGENCE if self.om_divergence else 0))
         s.seg_off = self.seg_off.data_ptr()
         s.seg_off_host = self.seg_off_host.ctypes.data
         s.dt = self.dt.data_ptr()
@@ -238,12 +244,12 @@ def _nat(p, r, natural):
 
 
 def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, arith="f64",
-                          chunk=0, check_finite=False):
+                          chunk=0, check_finite=False, om_divergence=False):
     """Device-resident Problem from a `workloads.Workload`-like object."""
     return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
                    theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
                    lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith,
-                   chunk=chunk, check_finite=check_finite)
+                   chunk=chunk, check_finite=check_finite, om_divergence=om_divergence)
 
 
 def autotune(p: Problem, cache_path=None) -> int:

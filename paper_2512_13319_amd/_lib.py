@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libmapscan.so")
 
 MAP_F32, MAP_F64, MAP_F32_FAST = 0, 1, 2
 MAP_CHECK_FINITE = 1
+MAP_OM_DIVERGENCE = 2
 MODELS = {"linear": 0, "cv": 1, "vdp": 2, "lorenz63": 3, "ct": 4}
 STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: "MAP_E_LAYOUT",
           -5: "MAP_E_NUMERIC", -6: "MAP_E_HIP", -7: "MAP_E_WORKSPACE", -8: "MAP_E_UNSUPPORTED"}

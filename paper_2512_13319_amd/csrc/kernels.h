@@ -580,17 +580,39 @@ struct Cursor {
     }
   }
 
-  // Adjoint problem (Ift<M>): the fresh element of the step ending at the
-  // fetched state has b = 0 and eta = g there; the prior's eta is g at the
-  // segment's first state.  No-ops for every other model.
+  // Changes to the fresh element of the step ending at the fetched state:
+  //  - adjoint problem (Ift<M>): b = 0 and eta = g there (the prior's eta is g
+  //    at the segment's first state, ift_prior);
+  //  - MAP_OM_DIVERGENCE with a state-dependent divergence: the Newton
+  //    expansion of 1/2 dt div f about xbar (M::div_newton).
+  // No-ops otherwise.
   template <int NW_>
-  MS_DEVONLY void ift_fresh(const Raw& r, Fresh<T, NX, NW_>& f) const {
+  MS_DEVONLY void ift_fresh(const Prob<TS>& p, const Raw& r, Fresh<T, NX, NW_>& f) const {
+    if constexpr (M::kDivNewton) {
+      if (p.om_div) {
+        T xb[NX];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) xb[c] = T(r.xb[c]);
+        M::div_newton(th, xb, T(r.dt), f.J, f.eta);
+      }
+    }
     if constexpr (M::kIft) {
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
         f.b[c] = T(0);
         f.eta[c] = T(r.g[c]);
       }
+    }
+  }
+  // divergence of the drift of a step (its terms st) at x, for the objective
+  MS_DEVONLY T divergence(const Step<T, NX, NY, NW>& st, const T (&x)[NX]) const {
+    if constexpr (M::NTH > 0) {
+      return M::divergence(th, x);
+    } else {
+      T tr = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) tr += st.F[c][c];
+      return tr;
     }
   }
   MS_DEVONLY void ift_prior(const Raw& r, T (&v0)[NX]) const {
@@ -1204,7 +1226,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
           rc.meas(y);
           Fresh<T, N, M::NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(rc, f);
+          cur.ift_fresh(p, rc, f);
           fold_fresh(agg, f);
         }
         if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
@@ -1420,7 +1442,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           cur.terms(p, i, rc, st);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(rc, f);
+          cur.ift_fresh(p, rc, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           if (kTraj && !first) {
             info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
@@ -1477,7 +1499,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           rc.meas(y);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(rc, f);
+          cur.ift_fresh(p, rc, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           aff_append(sagg, G, beta, Lam);
@@ -1503,7 +1525,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         rn.meas(y);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
-        cur.ift_fresh(rn, f);
+        cur.ift_fresh(p, rn, f);
         T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
         info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
         aff_append(sagg, G, beta, Lam);
@@ -1678,7 +1700,7 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
     cur.terms(p, i + 1, rc, st);
     Fresh<T, N, NW> f;
     fresh_from_step(st, y, f);
-    cur.ift_fresh(rc, f);
+    cur.ift_fresh(p, rc, f);
     // trajectory map of state i (shares Z with the information step)
     T W[N][NW];
     mm(S, f.V, W);
@@ -1746,6 +1768,8 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
       mv(st.Rinv, eps, Re);
 #pragma unroll
       for (int a = 0; a < NY; ++a) ob += 0.5 * double(st.dt) * double(eps[a]) * double(Re[a]);
+      // MAP_OM_DIVERGENCE: the divergence term 1/2 dt div f(x*) of eq. OM
+      if (p.om_div) ob += 0.5 * double(st.dt) * double(cur.divergence(st, xn));
       val[0] += ob;
       if constexpr (kGrad && M::NTH > 0) {
         // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T

@@ -141,7 +141,8 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
                 "chunk = %d; must be 0 (library's choice), 4, 8, 16, 32 or "
                 "MAP_SCHED_SEGMENT_WAVE (-1)",
                 p.chunk);
-  if (p.flags & ~MAP_CHECK_FINITE) return fail(MAP_E_ARG, "unknown flags 0x%x", unsigned(p.flags));
+  if (p.flags & ~(MAP_CHECK_FINITE | MAP_OM_DIVERGENCE))
+    return fail(MAP_E_ARG, "unknown flags 0x%x", unsigned(p.flags));
   const int nth = model_ntheta(p);
   if (nth < 0)
     return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
@@ -181,6 +182,17 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
       if (strides[i] < 0) return fail(MAP_E_ARG, "negative stride for matrix %d", i);
     }
   }
+  return MAP_OK;
+}
+
+// MAP_OM_DIVERGENCE changes the minimised objective (eq. OM with its
+// divergence term): the prediction-error likelihood and the gradients, which
+// refer to the energy objective and the probabilistic model, are not defined
+// with it, and the two-filter form's backward filter does not include it.
+map_status check_divergence(const map_problem& p, bool wants_ll_or_grad, const char* what) {
+  if ((p.flags & MAP_OM_DIVERGENCE) && wants_ll_or_grad)
+    return fail(MAP_E_UNSUPPORTED, "%s: MAP_OM_DIVERGENCE gives x*, P^s and the objective only "
+                                   "(no log-likelihood or gradients)", what);
   return MAP_OK;
 }
 
@@ -417,6 +429,7 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr) return fail(MAP_E_ARG, "S/v is NULL");
   if ((m == nullptr) != (P == nullptr)) return fail(MAP_E_ARG, "m and P must be given together");
+  if ((s = check_divergence(*p, loglik != nullptr, "map_filter_scan")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
@@ -442,6 +455,7 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_smooth")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, true)};
@@ -456,6 +470,8 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_smooth_noalloc")) != MAP_OK)
+    return s;
   const int chunk = sched::resolve(*p, true);
   const size_t need = sched::ws_need(*p, chunk);
   if (need > kScratchBytes)
@@ -479,6 +495,8 @@ map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* x
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if (p->flags & MAP_OM_DIVERGENCE)
+    return fail(MAP_E_UNSUPPORTED, "map_two_filter_smooth: MAP_OM_DIVERGENCE is not supported");
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
@@ -497,6 +515,8 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
   if (xbar_buf == xs) return fail(MAP_E_ARG, "xbar_buf must not alias xs");
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_iterated_nonlinear")) != MAP_OK)
+    return s;
   if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t ns = p->n_steps + p->n_seg;
@@ -547,6 +567,7 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
           return fail(MAP_E_ARG, "xs, mu and vmu must be distinct and not alias S, v or g_xs");
   }
   if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
+  if ((s = check_divergence(*p, true, "map_backward")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
@@ -563,7 +584,7 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
   if (s != MAP_OK) return s;
   if (chunk_out == nullptr) return fail(MAP_E_ARG, "chunk_out is NULL");
   map_problem q = *p;
-  q.flags &= ~MAP_CHECK_FINITE;  // timing runs check nothing
+  q.flags &= ~(MAP_CHECK_FINITE | MAP_OM_DIVERGENCE);  // timing runs: every output, nothing checked
   q.chunk = 0;
   if (ws == nullptr || ws_bytes < sched::ws_bytes_for(q))
     return fail(MAP_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,

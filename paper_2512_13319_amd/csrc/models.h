@@ -46,6 +46,7 @@ struct Prob {
   int64_t th_stride;
   const T* xbar;           // [nx][n_states] linearisation states (nonlinear models)
   const T* gx;             // [nx][n_states] cotangent of x* (the problem Ift<M> only)
+  int om_div;              // MAP_OM_DIVERGENCE: the divergence term of eq. OM is included
   // general linear model: row-major per-step matrices, stride 0 = shared by all steps
   const T *F, *c, *L, *W, *H, *r, *R;
   int64_t sF, sc, sL, sW, sH, sr, sR;
@@ -86,6 +87,13 @@ struct ModelCV {
     }
 #pragma unroll
     for (int i = 0; i < NX; ++i) s.c[i] = T(0);
+  }
+
+  // divergence of the drift (eq. OM): trace F = -D gamma, state independent
+  static constexpr bool kDivNewton = false;
+  template <typename T>
+  static MS_DEV T divergence(const T* th, const T (&)[NX]) {
+    return -T(D) * th[0];
   }
 
   // theta-cotangent of the element parameters: A = I - dt F(theta),
@@ -142,6 +150,22 @@ struct ModelVdP {
     s.Rinv[0][0] = rcp(rr);
   }
 
+  // divergence of the drift (eq. OM): d f2 / d x2 = mu (1 - x1^2), state
+  // dependent.  Newton treatment of the term 1/2 dt div f(x_k) of the
+  // discretised objective: its second-order expansion about xbar, added to
+  // the step's element as J += 1/2 dt Hess, eta -= 1/2 dt (grad - Hess xbar)
+  // with grad = (-2 mu x1, 0), Hess = diag(-2 mu, 0); the term is quadratic
+  // in x, so the expansion is exact (eta is unchanged).
+  static constexpr bool kDivNewton = true;
+  template <typename T>
+  static MS_DEV T divergence(const T* th, const T (&x)[NX]) {
+    return th[0] * (T(1) - x[0] * x[0]);
+  }
+  template <typename T>
+  static MS_DEV void div_newton(const T* th, const T (&)[NX], T dt, T (&J)[NX][NX], T (&)[NX]) {
+    J[0][0] -= dt * th[0];
+  }
+
   template <typename T>
   static MS_DEV void vjp(const T* th, const T (&x)[NX], T dt, const T (&GA)[NX][NX],
                          const T (&Gb)[NX], const T (&GC)[NX][NX], const T (&GR)[NY][NY],
@@ -194,6 +218,13 @@ struct ModelLorenz63 {
     }
   }
 
+  // divergence of the drift (eq. OM): -(sigma + 1 + beta), state independent
+  static constexpr bool kDivNewton = false;
+  template <typename T>
+  static MS_DEV T divergence(const T* th, const T (&)[NX]) {
+    return -(th[0] + T(1) + th[2]);
+  }
+
   template <typename T>
   static MS_DEV void vjp(const T* th, const T (&x)[NX], T dt, const T (&GA)[NX][NX],
                          const T (&)[NX], const T (&GC)[NX][NX], const T (&GR)[NY][NY],
@@ -221,6 +252,7 @@ struct ModelLinear {
   static constexpr bool kAdjoint = false;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = -1;
+  static constexpr bool kDivNewton = false;  // divergence trace F of the step (Cursor)
 };
 
 // ------------------------------------------------------------------ coordinated turn
@@ -241,6 +273,12 @@ struct ModelCT {
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr int kAngle = 1;
+  // divergence of the drift (eq. OM): zero (the turn rotates the velocity)
+  static constexpr bool kDivNewton = false;
+  template <typename T>
+  static MS_DEV T divergence(const T*, const T (&)[NX]) {
+    return T(0);
+  }
 
   template <typename T>
   static MS_DEV void terms(const T* th, const T (&x)[NX], T dt, Step<T, NX, NY, NW>& s) {

@@ -24,6 +24,7 @@ inline Prob<T> make_prob(const map_problem& q) {
   p.th_stride = q.theta_stride;
   p.xbar = static_cast<const T*>(q.xbar);
   p.gx = nullptr;
+  p.om_div = (q.flags & MAP_OM_DIVERGENCE) ? 1 : 0;
   p.F = static_cast<const T*>(q.F);
   p.c = static_cast<const T*>(q.c);
   p.L = static_cast<const T*>(q.L);

@@ -105,11 +105,24 @@ def test_workspace_bytes_by_schedule(seg):
 
 
 def test_flags_are_validated(seg):
-    """Only MAP_CHECK_FINITE is a known flag; other bits are rejected before any
-    launch."""
+    """MAP_CHECK_FINITE and MAP_OM_DIVERGENCE are the known flags; other bits
+    are rejected before any launch, and MAP_OM_DIVERGENCE rejects the
+    log-likelihood, gradients, the adjoint entry point and the two-filter
+    form."""
     lib = _lib.load()
     p = good(seg)
-    p.flags = 2
+    p.flags = _lib.MAP_OM_DIVERGENCE
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, FAKE, FAKE, 1 << 40,
+                               None) == -8
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, None, FAKE,
+                          1 << 40, None) == -8
+    assert lib.map_two_filter_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE,
+                                     1 << 40, None) == -8
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, None, None,
+                            None, None, None, FAKE, 1 << 40, None) == -8
+    assert b"MAP_OM_DIVERGENCE" in lib.map_last_error()
+    assert "#define MAP_OM_DIVERGENCE %d" % _lib.MAP_OM_DIVERGENCE in open(HEADER).read()
+    p.flags = 4
     assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                None) == -1
     assert b"flags" in lib.map_last_error()

@@ -863,3 +863,59 @@ def test_lorenz_gauss_newton_matches_nonlinear_least_squares():
                                     seg["m0"], seg["P0"], 3)
     g, = torch.autograd.grad(M, x)
     assert g.abs().max().item() < 1e-6
+
+
+# ------------------------------------------------------------------ divergence term of eq. OM
+
+@pytest.mark.parametrize("model", ["cv", "vdp", "lorenz63", "ct"])
+def test_divergence_is_the_trace_of_the_drift_jacobian(model):
+    """div f used by the Onsager--Machlup objective equals the trace of the
+    drift's Jacobian by central differences of f itself."""
+    from oracle import models
+    nx = {"cv": 4, "vdp": 2, "lorenz63": 3, "ct": 5}[model]
+    theta = torch.tensor({"cv": [0.3, 0.5, 0.05], "vdp": [1.5, 0.1, 0.05],
+                          "lorenz63": [10.0, 28.0, 8.0 / 3.0, 0.5, 0.5],
+                          "ct": [5e-4, 0.02, 5e-3, 1e-3]}[model], dtype=torch.float64)
+    rng = np.random.default_rng(81)
+    x = torch.tensor(rng.normal(0, 2, (7, nx)))
+    div = models.divergence_torch(model, theta, x, nx)
+    h = 1e-5
+    tr = torch.zeros(7, dtype=torch.float64)
+    for i in range(nx):
+        e = torch.zeros(nx, dtype=torch.float64)
+        e[i] = h
+        fp, _ = models.drift_torch(model, theta, x + e, nx)
+        fm, _ = models.drift_torch(model, theta, x - e, nx)
+        tr += (fp[:, i] - fm[:, i]) / (2 * h)
+    assert torch.allclose(div, tr, rtol=1e-8, atol=1e-8), (div, tr)
+
+
+def test_om_newton_iteration_reaches_the_minimiser_of_the_om_objective():
+    """Gauss--Newton on the energy part with a Newton step on the divergence
+    term (Van der Pol, state-dependent divergence mu (1 - x1^2)) converges to
+    the minimiser of the discretised Onsager--Machlup objective with its
+    divergence term, found by a generic quasi-Newton minimiser; the objective
+    decreases and its gradient vanishes there.  Without the term the iteration
+    converges to a different point (the term matters)."""
+    wl = workloads.vdp(T=40, dt=0.02, seed=82, n_iter=10)
+    seg = ref.workload_segment(wl, 0)
+    args = (seg["dt"], seg["y"], seg["m0"], seg["P0"], 2)
+    its, out = ref.gauss_newton("vdp", seg["theta"], *args, 10, om_div=True)
+    obj = [ref.om_objective("vdp", seg["theta"], x, *args).item() for x in its]
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(obj[1:], obj[2:])), obj
+    x = its[-1].clone().requires_grad_(True)
+    g, = torch.autograd.grad(ref.om_objective("vdp", seg["theta"], x, *args), x)
+    assert g.abs().max().item() < 1e-8, g.abs().max()
+
+    def fun(z):
+        t = torch.tensor(z.reshape(-1, 2), requires_grad=True)
+        val = ref.om_objective("vdp", seg["theta"], t, *args)
+        gr, = torch.autograd.grad(val, t)
+        return val.item(), gr.numpy().ravel()
+    res = scipy.optimize.minimize(fun, its[0].numpy().ravel(), jac=True, method="BFGS",
+                                  options={"gtol": 1e-11, "maxiter": 20000})
+    xm = res.x.reshape(-1, 2)
+    assert np.abs(xm - its[-1].numpy()).max() <= 1e-6 * np.abs(xm).max(), \
+        np.abs(xm - its[-1].numpy()).max()
+    its0, _ = ref.gauss_newton("vdp", seg["theta"], *args, 10, om_div=False)
+    assert np.abs(its0[-1].numpy() - its[-1].numpy()).max() > 1e-4
