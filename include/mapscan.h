@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 6
+#define MAPSCAN_ABI_VERSION 7
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
 /* map_problem.flags: minimise the Onsager--Machlup objective with its
@@ -177,6 +177,20 @@ typedef struct {
    * flag lives in the workspace, which the entry point leaves clear again.
    * Costs one stream synchronisation per call; without it nothing is checked. */
   int32_t flags;
+  /* Sub-stepped blocks (the paper's T blocks of n Euler substeps, Sec. 5.1):
+   * 0 or 1: one grid step is one explicit-Euler step of the element ODE
+   * (Sec. 4.2, eq. backwardLQT) from its boundary value, the element of every
+   * other entry; n_sub in [2, 64]: each grid step is a block whose element is
+   * that ODE integrated by n_sub explicit-Euler substeps of length dt / n_sub
+   * (the A equation read as A' = -A (Q J + F)), the model's terms held over
+   * the block (linearised at its last state), substep j using the
+   * measurement at its end: y then holds ny * n_sub components per state,
+   * component j * ny + c being measurement c at the end of substep j + 1 of
+   * the block that ends at the state.  Built for the constant-velocity model
+   * (nx = 4) and Van der Pol, MAP_F64 and MAP_F32.  Filter, smoother and
+   * map_dense_output only: no log-likelihood, objective, gradients,
+   * two-filter form or MAP_OM_DIVERGENCE. */
+  int32_t n_sub;
 } map_problem;
 
 /* Size in bytes of the workspace every scan entry needs for this problem
@@ -264,6 +278,25 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
 map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps,
                                  double* loglik, void* ws, size_t ws_bytes, void* stream);
 
+/* Dense output of sub-stepped blocks (n_sub >= 2): the filter and the MAP
+ * state at the n_sub - 1 interior substep times of every block, from the
+ * filter planes S, v and the block-boundary MAP states xs of map_smooth (or
+ * map_filter_scan + map_smoother_scan) on the same problem.  The filter at
+ * substep j is the filter at the block's start carried through the block's
+ * partial element of its first j substeps (Sec. 4.1 rule); the MAP states
+ * follow the paper's first recovery method (Sec. 3.5, Sec. 4.3): the closed-
+ * loop ODE of the optimal trajectory, in original time
+ * d/dt x* = (F + Q S) x* - Q v + c, integrated by explicit Euler backwards
+ * from the block's end, each substep using the filter at its later end.
+ *   xd  out, tiled [nx * (n_sub - 1)] per state: component (j - 1) * nx + a is
+ *       x*_a at interior substep j of the block ending at the state
+ *   Sd  out, tiled [nx(nx+1)/2 * (n_sub - 1)] per state: the filter's S there
+ *   vd  out, tiled [nx * (n_sub - 1)] per state: the second filter plane there
+ *       (v, or the mean with FP32 storage, as map_filter_scan)
+ * Entries at a segment's first state are not written. */
+map_status map_dense_output(const map_problem* p, const void* S, const void* v, const void* xs,
+                            void* xd, void* Sd, void* vd, void* stream);
+
 /* Iterated Taylor linearisation (Sec. 4.4): xbar^(0) = xbar0 (NULL: m0 of each
  * segment at every state), then n_iter times: linearise about xbar, solve
  * with map_smooth, xbar <- xs.  xbar_buf (tiled [nx] per state) is caller scratch that
@@ -349,7 +382,8 @@ map_status map_schedule(const map_problem* p, int32_t* chunk_out);
  * fix-up, 5 trajectory fix-up with adjoint, 6 auxiliary (zeroing), 7 filter
  * fix-up + backward-filter up-sweep (two-filter), 8 two-filter combination,
  * 9 the adjoint problem's passes (implicit-function VJP), 10 its per-step
- * cotangent reduction, 11 the segment-local fused step. */
+ * cotangent reduction, 11 the segment-local fused step, 12 dense output of
+ * sub-stepped blocks. */
 map_status map_profile_enable(int32_t capacity);
 map_status map_profile_reset(void);
 map_status map_profile_read(int32_t kind, int64_t* count, double* total_ms);

@@ -27,7 +27,7 @@ from ._lib import MapError, MODELS
 
 __all__ = ["Problem", "problem_from_workload", "filter_scan", "smoother_scan", "smooth",
            "two_filter_smooth", "autotune", "schedule", "lti_exact_terms",
-           "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth",
+           "iterated_nonlinear", "backward", "build_elements", "sym_to_full", "MapSmooth", "dense_output",
            "MapError", "N_THETA", "to_tiled", "from_tiled", "tiled_numel", "GraphedSmooth"]
 
 N_THETA = {"linear": 0, "cv": 3, "vdp": 3, "lorenz63": 5, "ct": 4}
@@ -116,12 +116,17 @@ class Problem:
     om_divergence  minimise the Onsager--Machlup objective with its divergence
               term (a Newton step on it where it depends on the state); x*,
               P^s and the objective only (see MAP_OM_DIVERGENCE)
+    n_sub     substeps per step (>= 2: each step is a block whose element is the
+              element ODE integrated by n_sub Euler substeps; y is then
+              [ny * n_sub, n_steps], component j * ny + c at the end of substep
+              j + 1); see `dense_output`
     """
 
     def __init__(self, model, nx, ny, nw, seg_off, dt, y, m0, P0, theta=None, xbar=None, lin=None,
                  dtype=torch.float64, device="cuda", arith="f64", chunk=0, check_finite=False,
-                 om_divergence=False):
+                 om_divergence=False, n_sub=1):
         _lib.load()
+        self.n_sub = int(n_sub)
         self.chunk = int(chunk)
         self.check_finite = bool(check_finite)
         self.om_divergence = bool(om_divergence)
@@ -146,7 +151,8 @@ class Problem:
         else:
             self.dt = to_tiled(t(steps_to_states(so, self.n_states, dt_np[None])))
         y_np = np.asarray(y.cpu().numpy() if torch.is_tensor(y) else y, dtype=np.float64)
-        self.y = to_tiled(t(steps_to_states(so, self.n_states, y_np.reshape(ny, self.n_steps))))
+        ny_all = ny * max(self.n_sub, 1)
+        self.y = to_tiled(t(steps_to_states(so, self.n_states, y_np.reshape(ny_all, self.n_steps))))
         m0 = t(m0)
         P0 = t(P0)
         self.m0 = m0.reshape(-1, nx)
@@ -178,6 +184,7 @@ class Problem:
         s.chunk = self.chunk
         s.flags = ((_lib.MAP_CHECK_FINITE if self.check_finite else 0)
                    | (_lib.MAP_OM_DIVERGENCE if self.om_divergence else 0))
+        s.n_sub = self.n_sub
         s.seg_off = self.seg_off.data_ptr()
         s.seg_off_host = self.seg_off_host.ctypes.data
         s.dt = self.dt.data_ptr()
@@ -249,7 +256,8 @@ def problem_from_workload(wl, dtype=torch.float64, device="cuda", xbar=None, ari
     return Problem(wl.model, wl.nx, wl.ny, wl.nw, wl.seg_off, wl.dt, wl.y, wl.m0, wl.P0,
                    theta=wl.theta if wl.model != "linear" else None, xbar=xbar,
                    lin=getattr(wl, "lin", None), dtype=dtype, device=device, arith=arith,
-                   chunk=chunk, check_finite=check_finite, om_divergence=om_divergence)
+                   chunk=chunk, check_finite=check_finite, om_divergence=om_divergence,
+                   n_sub=getattr(wl, "n_sub", 1))
 
 
 def autotune(p: Problem, cache_path=None) -> int:
@@ -375,6 +383,25 @@ def two_filter_smooth(p: Problem, covariances=True, loglik=True, out=None, natur
     _lib.check(lib.map_two_filter_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs),
                                          _ptr(Ps), _ptr(ll), _ptr(ws), ws.numel(), _stream()))
     return _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll), natural)
+
+
+def dense_output(p: Problem, S, v, xs, natural=True):
+    """Sub-stepped blocks: filter and MAP state at the interior substeps of
+    every block from tiled S, v, xs of `smooth` (natural=False).  Returns
+    xd [(n_sub-1), nx, n_states], Sd [(n_sub-1), nsym, n_states],
+    vd [(n_sub-1), nx, n_states] (natural) or the tiled buffers."""
+    lib = _lib.load()
+    k = p.n_sub - 1
+    xd = p._tiled(p.nx * k)
+    Sd = p._tiled(p.nsym * k)
+    vd = p._tiled(p.nx * k)
+    _lib.check(lib.map_dense_output(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(xd),
+                                    _ptr(Sd), _ptr(vd), _stream()))
+    if not natural:
+        return dict(xd=xd, Sd=Sd, vd=vd)
+    return dict(xd=p.natural(xd, p.nx * k).reshape(k, p.nx, p.n_states),
+                Sd=p.natural(Sd, p.nsym * k).reshape(k, p.nsym, p.n_states),
+                vd=p.natural(vd, p.nx * k).reshape(k, p.nx, p.n_states))
 
 
 def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, loglik=True,

@@ -16,13 +16,13 @@ STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: 
 
 # every symbol include/mapscan.h declares
 EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "map_filter_scan",
-           "map_smoother_scan", "map_smooth", "map_smooth_noalloc", "map_two_filter_smooth", "map_iterated_nonlinear",
+           "map_smoother_scan", "map_smooth", "map_smooth_noalloc", "map_two_filter_smooth", "map_dense_output", "map_iterated_nonlinear",
            "map_backward",
            "map_autotune", "map_lti_exact_terms", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
            "map_last_error", "map_abi_version"]
 PROF_KINDS = {"filter_up": 0, "filter_down": 1, "fused_down": 2, "traj_up": 3, "traj_down": 4,
               "traj_down_adjoint": 5, "aux": 6, "two_filter_up": 7, "two_filter_down": 8,
-              "ift_solve": 9, "ift_grad": 10, "seg_wave": 11}
+              "ift_solve": 9, "ift_grad": 10, "seg_wave": 11, "dense": 12}
 MAP_SCHED_SEGMENT_WAVE = -1
 
 
@@ -46,6 +46,7 @@ class MapProblem(ctypes.Structure):
         ("R_stride", ctypes.c_int64),
         ("chunk", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("n_sub", ctypes.c_int32),
     ]
 
 
@@ -77,6 +78,7 @@ def load(path: str | None = None):
     lib.map_smoother_scan.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_smooth.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.map_smooth_noalloc.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp]
+    lib.map_dense_output.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     lib.map_two_filter_smooth.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_iterated_nonlinear.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, vp, sz, vp]

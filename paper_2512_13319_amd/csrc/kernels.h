@@ -580,14 +580,21 @@ struct Cursor {
     }
   }
 
-  // Changes to the fresh element of the step ending at the fetched state:
-  //  - adjoint problem (Ift<M>): b = 0 and eta = g there (the prior's eta is g
-  //    at the segment's first state, ift_prior);
+  // Changes to the fresh element of the step that ends at state i (its
+  // fetched inputs r, terms st):
+  //  - sub-stepped blocks (Blocked<M>, n_sub > 1): the element of the block
+  //    integrated over its substeps (block_fresh) replaces the one-step one;
   //  - MAP_OM_DIVERGENCE with a state-dependent divergence: the Newton
-  //    expansion of 1/2 dt div f about xbar (M::div_newton).
+  //    expansion of 1/2 dt div f about xbar (M::div_newton);
+  //  - adjoint problem (Ift<M>): b = 0 and eta = g there (the prior's eta is g
+  //    at the segment's first state, ift_prior).
   // No-ops otherwise.
   template <int NW_>
-  MS_DEVONLY void ift_fresh(const Prob<TS>& p, const Raw& r, Fresh<T, NX, NW_>& f) const {
+  MS_DEVONLY void adjust_fresh(const Prob<TS>& p, int64_t i, const Raw& r,
+                               const Step<T, NX, NY, NW_>& st, Fresh<T, NX, NW_>& f) const {
+    if constexpr (M::kBlocked) {
+      if (p.n_sub > 1) block_fresh(p, i, st, f);
+    }
     if constexpr (M::kDivNewton) {
       if (p.om_div) {
         T xb[NX];
@@ -603,6 +610,107 @@ struct Cursor {
         f.eta[c] = T(r.g[c]);
       }
     }
+  }
+
+  // Element of a block of n_sub explicit-Euler substeps of length h = dt /
+  // n_sub of the element ODE (Sec. 4.2, eq. backwardLQT, written in original
+  // time, with the A equation read as A' = -A (Q J + F)), from the boundary
+  // value (I, 0, 0, 0, 0); substep j uses the measurement at its end
+  // (component j * NY + c of y at the block's last state):
+  //   A' = -A (Q J + F)               b' = A (Q eta - c)      C' = A Q A^T
+  //   eta' = -F^T eta - J Q eta + J c + H^T R^{-1} (y_j - r)
+  //   J' = -F^T J - J F - J Q J + H^T R^{-1} H.
+  // One substep reproduces the one-step element.  Substeps 1..k give the
+  // block's partial element up to its k-th substep (Euler, the dense output).
+  struct Block {
+    T A[NX][NX], b[NX], C[NX][NX], eta[NX], J[NX][NX];
+    T Q[NX][NX], HRH[NX][NX], RH[NY][NX], h;
+    template <int NW_>
+    MS_DEVONLY void begin(const Step<T, NX, NY, NW_>& st, int n) {
+      h = st.dt * rcp(T(n));
+      const T rdt = rcp(st.dt);
+      mmt_sym(st.V, st.V, Q);
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int q = 0; q < NX; ++q) Q[a][q] *= rdt;
+      mm(st.Rinv, st.H, RH);
+      mtm_sym(st.H, RH, HRH);
+      meye(A);
+      mzero(C);
+      mzero(J);
+#pragma unroll
+      for (int a = 0; a < NX; ++a) b[a] = eta[a] = T(0);
+    }
+    template <int NW_>
+    MS_DEVONLY void substep(const Step<T, NX, NY, NW_>& st, const T (&y)[NY]) {
+      T e[NY], g[NX];
+#pragma unroll
+      for (int c = 0; c < NY; ++c) e[c] = y[c] - st.r[c];
+      mtv(RH, e, g);  // H^T R^{-1} (y - r)
+      T QJ[NX][NX], QJF[NX][NX], dA[NX][NX], AQ[NX][NX], dC[NX][NX];
+      mm(Q, J, QJ);
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int q = 0; q < NX; ++q) QJF[a][q] = QJ[a][q] + st.F[a][q];
+      mm(A, QJF, dA);
+      mm(A, Q, AQ);
+      mmt_sym(AQ, A, dC);
+      T Qe[NX], db[NX];
+      mv(Q, eta, Qe);
+#pragma unroll
+      for (int a = 0; a < NX; ++a) Qe[a] -= st.c[a];
+      mv(A, Qe, db);
+      T Fe[NX], JQe[NX], Jc[NX], JQ[NX][NX], JQJ[NX][NX], FJ[NX][NX];
+      mtv(st.F, eta, Fe);
+      mtv(QJ, eta, JQe);  // (Q J)^T eta = J Q eta
+      mv(J, st.c, Jc);
+      mtm(QJ, J, JQJ);    // J Q J
+      mtm(st.F, J, FJ);   // F^T J
+#pragma unroll
+      for (int a = 0; a < NX; ++a) {
+        b[a] = fma_(h, db[a], b[a]);
+        eta[a] += h * (g[a] + Jc[a] - Fe[a] - JQe[a]);
+      }
+      T Jn[NX][NX];
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+          A[a][q] = fma_(-h, dA[a][q], A[a][q]);
+          C[a][q] = fma_(h, dC[a][q], C[a][q]);
+          // -F^T J - J F = -(F^T J) - (F^T J)^T
+          Jn[a][q] = J[a][q] + h * (HRH[a][q] - FJ[a][q] - FJ[q][a] - JQJ[a][q]);
+        }
+      mcopy(Jn, J);
+      (void)JQ;
+    }
+  };
+  MS_DEVONLY void block_meas(const Prob<TS>& p, int64_t i, int j, T (&y)[NY]) const {
+    const int C = NY * p.n_sub;
+#pragma unroll
+    for (int c = 0; c < NY; ++c) y[c] = T(p.y[tix(i, j * NY + c, C)]);
+  }
+  template <int NW_>
+  MS_DEVONLY void block_fresh(const Prob<TS>& p, int64_t i, const Step<T, NX, NY, NW_>& st,
+                              Fresh<T, NX, NW_>& f) const {
+    static_assert(NW_ == NX, "a block's noise factor is NX wide");
+    Block blk;
+    blk.begin(st, p.n_sub);
+    for (int j = 0; j < p.n_sub; ++j) {
+      T y[NY];
+      block_meas(p, i, j, y);
+      blk.substep(st, y);
+    }
+    mcopy(blk.A, f.A);
+    mcopy(blk.J, f.J);
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+      f.b[a] = blk.b[a];
+      f.eta[a] = blk.eta[a];
+    }
+    psd_factor(blk.C, f.V);
   }
   // divergence of the drift of a step (its terms st) at x, for the objective
   MS_DEVONLY T divergence(const Step<T, NX, NY, NW>& st, const T (&x)[NX]) const {
@@ -1226,7 +1334,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
           rc.meas(y);
           Fresh<T, N, M::NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(p, rc, f);
+          cur.adjust_fresh(p, i, rc, st, f);
           fold_fresh(agg, f);
         }
         if (cur.is_last(i) && i + 1 < p.n_states) cur.next(p);
@@ -1442,7 +1550,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           cur.terms(p, i, rc, st);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(p, rc, f);
+          cur.adjust_fresh(p, i, rc, st, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           if (kTraj && !first) {
             info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
@@ -1499,7 +1607,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
           rc.meas(y);
           Fresh<T, N, NW> f;
           fresh_from_step(st, y, f);
-          cur.ift_fresh(p, rc, f);
+          cur.adjust_fresh(p, i + 1, rc, st, f);
           T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
           info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
           aff_append(sagg, G, beta, Lam);
@@ -1525,7 +1633,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
         rn.meas(y);
         Fresh<T, N, NW> f;
         fresh_from_step(st, y, f);
-        cur.ift_fresh(p, rn, f);
+        cur.adjust_fresh(p, il + 1, rn, st, f);
         T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
         info_step<T, N, NW, true>(S, v, f, Sn, vn, Sp, G, beta, Lam);
         aff_append(sagg, G, beta, Lam);
@@ -1700,7 +1808,7 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
     cur.terms(p, i + 1, rc, st);
     Fresh<T, N, NW> f;
     fresh_from_step(st, y, f);
-    cur.ift_fresh(p, rc, f);
+    cur.adjust_fresh(p, i + 1, rc, st, f);
     // trajectory map of state i (shares Z with the information step)
     T W[N][NW];
     mm(S, f.V, W);
@@ -2224,10 +2332,14 @@ __global__ void __launch_bounds__(kBlock) k_build_elements(Prob<TS> p, TS* out) 
     for (int r = 0; r < N; ++r) e.b[r] = T(0);
   } else {
     Step<T, N, M::NY, M::NW> st;
+    typename Cursor<TS, T, M>::Raw r;
+    cur.fetch(p, i, r);
+    cur.terms(p, i, r, st);
     T y[M::NY];
-    cur.step(p, i, st, y);
+    r.meas(y);
     Fresh<T, N, M::NW> f;
     fresh_from_step(st, y, f);
+    cur.adjust_fresh(p, i, r, st, f);
     fresh_to_elem(f, e);
   }
   constexpr int C = ElemSz<N>::n;

@@ -297,6 +297,33 @@ MS_DEV void trsv_upper_t(const T (&l)[N][N], const T (&dinv)[N], T (&b)[N]) {
 }
 
 // Inverse of an SPD matrix through its Cholesky factor (symmetric result).
+// Lower-triangular l with l l^T = a for positive semidefinite a: Cholesky
+// that leaves a zero column where the pivot vanishes (at most a few ulp of the
+// diagonal), as for a covariance of less than full rank.
+template <typename T, int N>
+MS_DEV void psd_factor(const T (&a)[N][N], T (&l)[N][N]) {
+  constexpr T kRel = sizeof(T) == 8 ? T(1e-13) : T(1e-6);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T s = a[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = fma_(-l[j][k], l[j][k], s);
+    const bool pos = s > kRel * a[j][j];
+    T d, di;
+    sqrt_rsqrt(pos ? s : T(1), d, di);
+    l[j][j] = pos ? d : T(0);
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      T t = a[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = fma_(-l[i][k], l[j][k], t);
+      l[i][j] = pos ? t * di : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) l[i][j] = T(0);
+  }
+}
+
 template <typename T, int N>
 MS_DEV void spd_inv(const T (&a)[N][N], T (&out)[N][N]) {
   T l[N][N], dinv[N], li[N][N];

@@ -100,9 +100,27 @@ struct Entry {
   X(MAP_MODEL_LINEAR, 4, 4, 4, 0, ModelLinear<4 MS_COMMA 4 MS_COMMA 4>)
 #define MS_COMMA ,
 
+// Models built with sub-stepped blocks (Blocked<M>, n_sub > 1).
+#define MS_BLOCKED_MODELS(X)                      \
+  X(MAP_MODEL_CV, 4, 2, 2, 3, ModelCV<2>)         \
+  X(MAP_MODEL_VDP, 2, 1, 2, 3, ModelVdP)
+
 // Calls f.template run<T, M>() for the matching instantiation.
 template <class Fn>
 map_status dispatch(const map_problem& p, Fn&& f) {
+  if (p.n_sub > 1) {
+#define MS_BCASE(MODEL, NX, NY, NW, NTH, M)                                            \
+  if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) {                   \
+    if (p.dtype == MAP_F64) return f.template run<double, double, Blocked<M>>();      \
+    if (p.dtype == MAP_F32) return f.template run<float, double, Blocked<M>>();       \
+    return fail(MAP_E_UNSUPPORTED, "sub-stepped blocks need FP64 arithmetic (MAP_F64 or MAP_F32)"); \
+  }
+    MS_BLOCKED_MODELS(MS_BCASE)
+#undef MS_BCASE
+    return fail(MAP_E_UNSUPPORTED,
+                "sub-stepped blocks (n_sub > 1) are built for the constant-velocity model with "
+                "nx = 4 and for Van der Pol");
+  }
 #define MS_CASE(MODEL, NX, NY, NW, NTH, M)                                            \
   if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) {                   \
     if (p.dtype == MAP_F64) return f.template run<double, double, M>();               \
@@ -143,6 +161,9 @@ map_status validate(const map_problem* pp, bool need_xbar = true) {
                 p.chunk);
   if (p.flags & ~(MAP_CHECK_FINITE | MAP_OM_DIVERGENCE))
     return fail(MAP_E_ARG, "unknown flags 0x%x", unsigned(p.flags));
+  if (p.n_sub < 0 || p.n_sub > 64) return fail(MAP_E_ARG, "n_sub = %d outside [0, 64]", p.n_sub);
+  if (p.n_sub > 1 && (p.flags & MAP_OM_DIVERGENCE))
+    return fail(MAP_E_UNSUPPORTED, "sub-stepped blocks do not take MAP_OM_DIVERGENCE");
   const int nth = model_ntheta(p);
   if (nth < 0)
     return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
@@ -193,6 +214,16 @@ map_status check_divergence(const map_problem& p, bool wants_ll_or_grad, const c
   if ((p.flags & MAP_OM_DIVERGENCE) && wants_ll_or_grad)
     return fail(MAP_E_UNSUPPORTED, "%s: MAP_OM_DIVERGENCE gives x*, P^s and the objective only "
                                    "(no log-likelihood or gradients)", what);
+  return MAP_OK;
+}
+
+// Sub-stepped blocks: a block's element is not one measurement step, so the
+// prediction-error likelihood, the costate-form objective and the adjoint
+// (all written per measurement step) are not defined for it.
+map_status check_blocks(const map_problem& p, bool wants_ll_obj_or_grad, const char* what) {
+  if (p.n_sub > 1 && wants_ll_obj_or_grad)
+    return fail(MAP_E_UNSUPPORTED, "%s: sub-stepped blocks give the filter, x*, P^s and the "
+                                   "dense output only", what);
   return MAP_OK;
 }
 
@@ -387,6 +418,15 @@ struct DoIft {
     return hip_status(Runner<TS, T, M>::ift(p, a, b), "map_backward (implicit-function VJP)");
   }
 };
+struct DoDense {
+  const map_problem& p;
+  const void *S, *v, *xs;
+  void *xd, *Sd, *vd;
+  hipStream_t st;
+  template <typename TS, typename T, class M> map_status run() {
+    return hip_status(Runner<TS, T, M>::dense(p, S, v, xs, xd, Sd, vd, st), "map_dense_output");
+  }
+};
 struct DoInitX {
   const map_problem& p;
   void* xb;
@@ -430,6 +470,7 @@ map_status map_filter_scan(const map_problem* p, void* S, void* v, void* m, void
   if (S == nullptr || v == nullptr) return fail(MAP_E_ARG, "S/v is NULL");
   if ((m == nullptr) != (P == nullptr)) return fail(MAP_E_ARG, "m and P must be given together");
   if ((s = check_divergence(*p, loglik != nullptr, "map_filter_scan")) != MAP_OK) return s;
+  if ((s = check_blocks(*p, loglik != nullptr, "map_filter_scan")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, m, P, nullptr, nullptr, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
@@ -441,6 +482,7 @@ map_status map_smoother_scan(const map_problem* p, const void* S, const void* v,
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if ((s = check_blocks(*p, obj != nullptr, "map_smoother_scan")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
                nullptr, nullptr, ws, static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
@@ -456,6 +498,7 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_smooth")) != MAP_OK) return s;
+  if ((s = check_blocks(*p, loglik || obj || g_loglik || g_obj, "map_smooth")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, true)};
@@ -471,6 +514,8 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_smooth_noalloc")) != MAP_OK)
+    return s;
+  if ((s = check_blocks(*p, loglik || obj || g_loglik || g_obj, "map_smooth_noalloc")) != MAP_OK)
     return s;
   const int chunk = sched::resolve(*p, true);
   const size_t need = sched::ws_need(*p, chunk);
@@ -497,10 +542,23 @@ map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* x
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if (p->flags & MAP_OM_DIVERGENCE)
     return fail(MAP_E_UNSUPPORTED, "map_two_filter_smooth: MAP_OM_DIVERGENCE is not supported");
+  if ((s = check_blocks(*p, true, "map_two_filter_smooth")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
   return finish_check(*p, ws, a.stream, dispatch(*p, DoTwoFilter{*p, a}));
+}
+
+map_status map_dense_output(const map_problem* p, const void* S, const void* v, const void* xs,
+                            void* xd, void* Sd, void* vd, void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (p->n_sub < 2) return fail(MAP_E_ARG, "map_dense_output needs sub-stepped blocks (n_sub >= 2)");
+  if (S == nullptr || v == nullptr || xs == nullptr || xd == nullptr || Sd == nullptr ||
+      vd == nullptr)
+    return fail(MAP_E_ARG, "S/v/xs/xd/Sd/vd is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dispatch(*p, DoDense{*p, S, v, xs, xd, Sd, vd, st});
 }
 
 map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const void* xbar0,
@@ -516,6 +574,8 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
   if ((g_loglik != nullptr || g_obj != nullptr) && p->model == MAP_MODEL_LINEAR)
     return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_iterated_nonlinear")) != MAP_OK)
+    return s;
+  if ((s = check_blocks(*p, loglik || obj || g_loglik || g_obj, "map_iterated_nonlinear")) != MAP_OK)
     return s;
   if ((s = check_ws(*p, ws, ws_bytes, true)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -568,6 +628,7 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   }
   if (p->model == MAP_MODEL_LINEAR) return fail(MAP_E_UNSUPPORTED, "gradients need a parametric model");
   if ((s = check_divergence(*p, true, "map_backward")) != MAP_OK) return s;
+  if ((s = check_blocks(*p, true, "map_backward")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,

@@ -47,6 +47,7 @@ struct Prob {
   const T* xbar;           // [nx][n_states] linearisation states (nonlinear models)
   const T* gx;             // [nx][n_states] cotangent of x* (the problem Ift<M> only)
   int om_div;              // MAP_OM_DIVERGENCE: the divergence term of eq. OM is included
+  int n_sub;               // Euler substeps per grid step (Blocked<M> only; y holds ny * n_sub per state)
   // general linear model: row-major per-step matrices, stride 0 = shared by all steps
   const T *F, *c, *L, *W, *H, *r, *R;
   int64_t sF, sc, sL, sW, sH, sr, sR;
@@ -62,6 +63,7 @@ struct ModelCV {
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
+  static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr int kAngle = -1;  // no angular measurement component
 
   template <typename T>
@@ -123,6 +125,7 @@ struct ModelVdP {
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
+  static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -189,6 +192,7 @@ struct ModelLorenz63 {
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
+  static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -251,6 +255,7 @@ struct ModelLinear {
   static constexpr bool kNonlinear = false;
   static constexpr bool kAdjoint = false;
   static constexpr bool kIft = false;  // see Ift below
+  static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr int kAngle = -1;
   static constexpr bool kDivNewton = false;  // divergence trace F of the step (Cursor)
 };
@@ -272,6 +277,7 @@ struct ModelCT {
   static constexpr bool kNonlinear = true;
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
+  static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr int kAngle = 1;
   // divergence of the drift (eq. OM): zero (the turn rotates the velocity)
   static constexpr bool kDivNewton = false;
@@ -346,6 +352,50 @@ struct ModelCT {
 template <class M>
 struct Ift : M {
   static constexpr bool kIft = true;
+};
+
+// ------------------------------------------------------------------ sub-stepped blocks
+// A grid step [t_{k-1}, t_k] taken as a block of n_sub explicit-Euler substeps
+// of the element ODE (Sec. 4.2, eq. backwardLQT; the paper's T blocks of n
+// Euler substeps, Sec. 5.1) instead of one: see Cursor::block_fresh.  The
+// model's terms are held over the block (linearised at the block's right end
+// for nonlinear models).  A block's C has full rank, so the wrapper's noise
+// factor is NX wide (the base model's V, padded with zero columns, carries
+// Q = V V^T / dt).  Filter, smoother and dense output only (no adjoint, no
+// log-likelihood or objective).
+template <class M>
+struct Blocked : M {
+  static constexpr int NW = M::NX;
+  static constexpr bool kAdjoint = false;
+  static constexpr bool kBlocked = true;
+
+  template <typename T>
+  static MS_DEV void terms(const T* th, const T (&x)[M::NX], T dt,
+                           Step<T, M::NX, M::NY, M::NX>& s) {
+    Step<T, M::NX, M::NY, M::NW> b;
+    M::terms(th, x, dt, b);
+    s.dt = b.dt;
+#pragma unroll
+    for (int a = 0; a < M::NX; ++a) {
+      s.c[a] = b.c[a];
+#pragma unroll
+      for (int q = 0; q < M::NX; ++q) {
+        s.F[a][q] = b.F[a][q];
+        s.V[a][q] = q < M::NW ? b.V[a][q] : T(0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < M::NY; ++a) {
+      s.r[a] = b.r[a];
+#pragma unroll
+      for (int q = 0; q < M::NX; ++q) s.H[a][q] = b.H[a][q];
+#pragma unroll
+      for (int q = 0; q < M::NY; ++q) {
+        s.R[a][q] = b.R[a][q];
+        s.Rinv[a][q] = b.Rinv[a][q];
+      }
+    }
+  }
 };
 
 }  // namespace ms

@@ -126,7 +126,8 @@ enum ProfKind : int {
   kProfIftSolve = 9,
   kProfIftGrad = 10,
   kProfSegWave = 11,
-  kProfKinds = 12
+  kProfDense = 12,
+  kProfKinds = 13
 };
 void prof_begin(int kind, hipStream_t st);
 void prof_end(int kind, hipStream_t st);
@@ -141,6 +142,9 @@ struct Runner {
   static hipError_t two_filter(const map_problem& p, const SmoothArgs& a);
   // needs a.S, a.v (the filter planes) and a.xs (x*) of the problem
   static hipError_t ift(const map_problem& p, const SmoothArgs& a, const IftArgs& b);
+  // sub-stepped blocks: filter and MAP state at the interior substeps
+  static hipError_t dense(const map_problem& p, const void* S, const void* v, const void* xs,
+                          void* xd, void* Sd, void* vd, hipStream_t st);
   static hipError_t init_xbar(const map_problem& p, void* xbar, hipStream_t st);
 };
 

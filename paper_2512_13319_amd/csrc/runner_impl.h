@@ -3,6 +3,7 @@
 #include "kernels.h"
 #include "runner.h"
 #include "segwave.h"
+#include "blocks.h"
 
 namespace ms {
 
@@ -25,6 +26,7 @@ inline Prob<T> make_prob(const map_problem& q) {
   p.xbar = static_cast<const T*>(q.xbar);
   p.gx = nullptr;
   p.om_div = (q.flags & MAP_OM_DIVERGENCE) ? 1 : 0;
+  p.n_sub = q.n_sub > 1 ? q.n_sub : 1;
   p.F = static_cast<const T*>(q.F);
   p.c = static_cast<const T*>(q.c);
   p.L = static_cast<const T*>(q.L);
@@ -264,29 +266,48 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
 // Two-filter smoother: filter up-sweep, filter fix-up with the backward
 // filter's up-sweep, two-filter combination.
 template <typename TS, typename T, class M>
+hipError_t Runner<TS, T, M>::dense(const map_problem& q, const void* S, const void* v,
+                                   const void* xs, void* xd, void* Sd, void* vd, hipStream_t st) {
+  if constexpr (!M::kBlocked) {
+    return hipErrorInvalidValue;  // rejected by the entry point before this
+  } else {
+    Prob<TS> p = make_prob<TS>(q);
+    prof_begin(kProfDense, st);
+    k_dense<TS, T, M><<<unsigned((p.n_states + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        p, DenseIO{S, v, xs, xd, Sd, vd});
+    prof_end(kProfDense, st);
+    return hipGetLastError();
+  }
+}
+
+template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& a) {
-  Prob<TS> p = make_prob<TS>(q);
-  Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
-  const unsigned g = grid_for(w.n_tiles);
-  prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
-      p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
-  prof_end(kProfFilterUp, a.stream);
-  MS_CHECK(hipGetLastError());
-  FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
-  Acc acc{a.loglik, nullptr, nullptr, nullptr};
-  prof_begin(kProfTwoFilterUp, a.stream);
-  k_filter_down<TS, T, M, kModeTwoFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
-  prof_end(kProfTwoFilterUp, a.stream);
-  MS_CHECK(hipGetLastError());
-  TrajOut to{a.S, a.v, a.xs, a.Ps, 0, 0};
-  prof_begin(kProfTwoFilterDown, a.stream);
-  if (a.Ps != nullptr)
-    k_two_filter_down<TS, T, M, true><<<g, kBlock, 0, a.stream>>>(p, w, to);
-  else
-    k_two_filter_down<TS, T, M, false><<<g, kBlock, 0, a.stream>>>(p, w, to);
-  prof_end(kProfTwoFilterDown, a.stream);
-  return hipGetLastError();
+  if constexpr (M::kBlocked) {
+    return hipErrorInvalidValue;  // rejected by the entry point
+  } else {
+    Prob<TS> p = make_prob<TS>(q);
+    Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
+    const unsigned g = grid_for(w.n_tiles);
+    prof_begin(kProfFilterUp, a.stream);
+    k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
+        p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
+    prof_end(kProfFilterUp, a.stream);
+    MS_CHECK(hipGetLastError());
+    FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
+    Acc acc{a.loglik, nullptr, nullptr, nullptr};
+    prof_begin(kProfTwoFilterUp, a.stream);
+    k_filter_down<TS, T, M, kModeTwoFilter><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+    prof_end(kProfTwoFilterUp, a.stream);
+    MS_CHECK(hipGetLastError());
+    TrajOut to{a.S, a.v, a.xs, a.Ps, 0, 0};
+    prof_begin(kProfTwoFilterDown, a.stream);
+    if (a.Ps != nullptr)
+      k_two_filter_down<TS, T, M, true><<<g, kBlock, 0, a.stream>>>(p, w, to);
+    else
+      k_two_filter_down<TS, T, M, false><<<g, kBlock, 0, a.stream>>>(p, w, to);
+    prof_end(kProfTwoFilterDown, a.stream);
+    return hipGetLastError();
+  }
 }
 
 // Implicit-function VJP: mu = H^{-1} g by the smoother's three passes on the
@@ -334,5 +355,9 @@ hipError_t Runner<TS, T, M>::ift(const map_problem& q, const SmoothArgs& a, cons
   template struct Runner<double, double, M>; \
   template struct Runner<float, double, M>;  \
   template struct Runner<float, float, M>;
+// sub-stepped blocks: FP64 arithmetic only
+#define MS_INSTANTIATE_BLOCKED(M)            \
+  template struct Runner<double, double, Blocked<M>>; \
+  template struct Runner<float, double, Blocked<M>>;
 
 }  // namespace ms

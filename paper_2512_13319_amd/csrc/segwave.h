@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_wave(Prob<TS> p, SegOut o) {
             rc.meas(y);
             Fresh<T, N, NW> f;
             fresh_from_step(st, y, f);
-            cur.ift_fresh(p, rc, f);
+            cur.adjust_fresh(p, i, rc, st, f);
             fold_fresh(agg, f);
           }
         }
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_wave(Prob<TS> p, SegOut o) {
             cur.terms(p, i, rc, st);
             Fresh<T, N, NW> f;
             fresh_from_step(st, y, f);
-            cur.ift_fresh(p, rc, f);
+            cur.adjust_fresh(p, i, rc, st, f);
             T Sn[N][N], vn[N], Sp[N][N], G[N][N], beta[N], Lam[N][N];
             info_step<T, N, NW, false>(S, v, f, Sn, vn, Sp, G, beta, Lam);
             if (want_ll) {
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_wave(Prob<TS> p, SegOut o) {
             cur.terms(p, i + 1, q.r, st);
             Fresh<T, N, NW> f;
             fresh_from_step(st, y, f);
-            cur.ift_fresh(p, q.r, f);
+            cur.adjust_fresh(p, i + 1, q.r, st, f);
             traj_map(S, v, f, G, beta, Lam);
           }
           aff_append(sagg, G, beta, Lam);

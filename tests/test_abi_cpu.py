@@ -291,3 +291,36 @@ def test_lti_exact_terms_against_the_oracle():
     assert lib.map_lti_exact_terms(9, 2, p(F), None, p(L), p(L), 0.1, p(out), p(out), p(out)) == -2
     Fn = F.copy(); Fn[0, 0] = np.nan
     assert lib.map_lti_exact_terms(2, 2, p(Fn), None, p(L), p(L), 0.1, p(out), p(out), p(out)) == -5
+
+
+def test_substep_blocks_are_validated(seg):
+    """n_sub: [0, 64]; blocks are built for the constant-velocity model with
+    nx = 4 and for Van der Pol in FP64 arithmetic, give no log-likelihood,
+    objective, gradients, two-filter form or divergence term; the dense output
+    needs blocks.  All rejected on the host."""
+    lib = _lib.load()
+    p = good(seg)
+    p.n_sub = 65
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -1
+    p.n_sub = 10
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, FAKE, FAKE, 1 << 40,
+                               None) == -8
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, None, None, FAKE,
+                          1 << 40, None) == -8
+    assert lib.map_two_filter_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE,
+                                     1 << 40, None) == -8
+    p.flags = _lib.MAP_OM_DIVERGENCE
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, FAKE,
+                          1 << 40, None) == -8
+    p.flags = 0
+    p.dtype = _lib.MAP_F32_FAST
+    assert lib.map_dense_output(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -8
+    p.dtype = _lib.MAP_F64
+    p.model, p.nx, p.ny, p.nw, p.n_theta = _lib.MODELS["lorenz63"], 3, 3, 3, 5
+    p.m0_stride, p.P0_stride, p.theta_stride = 3, 9, 5
+    p.xbar = FAKE
+    assert lib.map_dense_output(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -8
+    q = good(seg)
+    q.n_sub = 1
+    assert lib.map_dense_output(ctypes.byref(q), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1

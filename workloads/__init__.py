@@ -52,6 +52,7 @@ class Workload:
     n_iter: int = 1            # Gauss--Newton iterations (1 for linear models)
     dtype: str = "f64"
     lin: dict | None = None    # model "linear": F [nx,nx] or [n_steps,nx,nx], c, L, W, H, r, R
+    n_sub: int = 1             # substeps per step (blocks): y is then [ny * n_sub, n_steps]
 
     @property
     def n_seg(self) -> int:
@@ -80,6 +81,28 @@ class Workload:
         lin = None if self.lin is None else {k: r(v) for k, v in self.lin.items()}
         return dataclasses.replace(self, dt=r(self.dt), y=r(self.y), theta=r(self.theta),
                                    m0=r(self.m0), P0=r(self.P0), dtype=dtype, lin=lin)
+
+
+def blocks(wl: Workload, n_sub: int) -> Workload:
+    """The same data regrouped into blocks of n_sub consecutive steps (each
+    segment's length must be a multiple of n_sub): a block's step length is
+    the sum of its substeps' (uniform within a block), its measurements are
+    those of its substeps in order (y [ny * n_sub, n_blocks], component
+    j * ny + c = measurement c at the end of substep j + 1), and x_true keeps
+    the block boundaries."""
+    lens = np.diff(wl.seg_off)
+    if np.any(lens % n_sub):
+        raise ValueError("segment lengths must be multiples of n_sub")
+    nb = lens // n_sub
+    seg_off = np.zeros_like(wl.seg_off)
+    seg_off[1:] = np.cumsum(nb)
+    ny = wl.ny
+    y = wl.y.T.reshape(-1, n_sub * ny).T.copy()
+    dt = wl.dt.reshape(-1, n_sub).sum(1)
+    keep = np.concatenate([wl.seg_off[s] + s + n_sub * np.arange(nb[s] + 1)
+                           for s in range(wl.n_seg)])
+    return dataclasses.replace(wl, name=wl.name + "_blocks%d" % n_sub, seg_off=seg_off, dt=dt,
+                               y=y, x_true=wl.x_true[:, keep], n_sub=n_sub)
 
 
 def _rng(seed: int) -> np.random.Generator:
