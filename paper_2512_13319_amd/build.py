@@ -48,7 +48,12 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     """Compile every translation unit (with incremental=True, only those whose
     object is older than the unit or any header) and link the library."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the largest units (general linear model at nx = 8, 7, ...) first, so that
+    # the parallel build does not end waiting on one of them
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")),
+                  key=lambda f: ("0" + str(9 - int(os.path.basename(f)[12]))
+                                 if os.path.basename(f).startswith("inst_linpad_")
+                                 and os.path.basename(f)[12].isdigit() else "1" + f))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda src: _compile(src, incremental), srcs))

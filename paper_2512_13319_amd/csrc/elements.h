@@ -113,12 +113,12 @@ MS_DEV void combine(const Elem<T, N>& E, const Elem<T, N>& L, Elem<T, N>& out) {
   T JMA[N][N];
   mm(E.J, MA, JMA);         // J_E M A_L  (= M^T J_E A_L)
   T Jn[N][N];
-  mtm_sym(L.A, JMA, Jn);    // A_L^T M^T J_E A_L
+  mtm_symavg(L.A, JMA, Jn);  // A_L^T M^T J_E A_L
   T MC[N][N], AMC[N][N];
   mm(M, L.C, MC);           // M C_L (symmetric)
   mm(E.A, MC, AMC);
   T Cn[N][N];
-  mmt_sym(AMC, E.A, Cn);    // A_E M C_L A_E^T
+  mmt_symavg(AMC, E.A, Cn);  // A_E M C_L A_E^T
   T u[N], Mu[N], t[N];
   mv(L.C, E.eta, u);
 #pragma unroll
@@ -144,7 +144,8 @@ MS_DEV void combine(const Elem<T, N>& E, const Elem<T, N>& L, Elem<T, N>& out) {
 }
 
 // agg <- agg . f  (fold a fresh element onto the right of a run).
-// With Z = I + V^T J_E V (SPD), M = I - V Z^{-1} V^T J_E, M C_L = V Z^{-1} V^T.
+// With W = J_E V, Z = I + V^T W (SPD), M = I - V Z^{-1} W^T, M C_L = V Z^{-1} V^T,
+// and X = Z^{-1} W^T A_L: M A_L = A_L - V X, A_L^T M^T J_E A_L = (M A_L)^T J_E (M A_L) + X^T X.
 template <typename T, int N, int NW>
 MS_DEV void fold_fresh(Elem<T, N>& E, const Fresh<T, N, NW>& f) {
   T W[N][NW];
@@ -204,10 +205,17 @@ MS_DEV void fold_fresh(Elem<T, N>& E, const Fresh<T, N, NW>& f) {
   T bn[N], en[N];
   mv(E.A, Mu, bn);
   mtv(f.A, Mtw, en);
-  // J = A_L^T (J_E T3) + J_L
-  T JT[N][N], Jn[N][N];
+  // J = A_L^T M^T J_E A_L + J_L in Joseph form, T3^T J_E T3 + X^T X + J_L
+  // (as in info_step: the difference J_E - W Z^{-1} W^T cancels where J_E is
+  // ill-conditioned)
+  T JT[N][N], Jn[N][N], XX[N][N];
   mm(E.J, T3, JT);
-  mtm_sym(f.A, JT, Jn);
+  mtm_sym(T3, JT, Jn);
+  mtm_sym(X, X, XX);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Jn[i][j] += XX[i][j];
   // C = (A_E V Lz^{-T}) (A_E V Lz^{-T})^T + C_E
   T AV[N][NW];
   mm(E.A, f.V, AV);
@@ -236,9 +244,15 @@ MS_DEV void fold_fresh(Elem<T, N>& E, const Fresh<T, N, NW>& f) {
 
 // Information step (S, v) . f -> (S', v'), and optionally the trajectory
 // element (G, beta, Lam) of the state that (S, v) belongs to, which shares
-// the factor Z = I + V^T S V:
-//   (I + S C)^{-1} S = S - W Z^{-1} W^T,  (I + S C)^{-1} = I - W Z^{-1} V^T,
-//   (I + C S)^{-1}   = I - V Z^{-1} W^T,  with W = S V.
+// the factor Z = I + V^T S V.  With W = S V and X = Z^{-1} W^T A:
+//   (I + C S)^{-1} A = A - V X = G,   (I + S C)^{-1} = I - W Z^{-1} V^T,
+//   A^T (I + S C)^{-1} S A = G^T S G + X^T X.
+// The last line is the Joseph form of A^T (S - W Z^{-1} W^T) A: a sum of two
+// PSD terms instead of a difference.  Where S is ill-conditioned (strongly
+// observed directions next to weakly observed ones) the difference loses
+// everything below eps |S|, and the recursion then amplifies that loss
+// through A = I - dt F step after step; the Joseph form keeps the small
+// eigenvalues to the accuracy of their own scale.
 template <typename T, int N, int NW, bool kTraj>
 MS_DEV void info_step(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>& f,
                       T (&Sn)[N][N], T (&vn)[N], T (&Sp)[N][N],
@@ -251,22 +265,28 @@ MS_DEV void info_step(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>
   for (int i = 0; i < NW; ++i) Z[i][i] += T(1);
   T Lz[NW][NW], dz[NW];
   chol(Z, Lz, dz);
-  // Nm = S - (Lz^{-1} W^T)^T (Lz^{-1} W^T)
-  T Yw[NW][N];
-#pragma unroll
-  for (int i = 0; i < NW; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) Yw[i][j] = W[j][i];
-  trsm_lower(Lz, dz, Yw);
-  T Nm[N][N];
-  mtm_sym(Yw, Yw, Nm);
+  // X = Z^{-1} W^T A,  G = A - V X
+  T X[NW][N];
+  mtm(W, f.A, X);
+  trsm_lower(Lz, dz, X);
+  trsm_upper_t(Lz, dz, X);
+  T Gm[N][N];
+  mm(f.V, X, Gm);
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) Nm[i][j] = S[i][j] - Nm[i][j];
-  T NA[N][N];
-  mm(Nm, f.A, NA);
-  mtm_sym(f.A, NA, Sp);  // predicted information A^T (S^{-1} + C)^{-1} A
+    for (int j = 0; j < N; ++j) Gm[i][j] = f.A[i][j] - Gm[i][j];
+  // predicted information A^T (S^{-1} + C)^{-1} A = G^T S G + X^T X
+  {
+    T SG[N][N], XX[N][N];
+    mm(S, Gm, SG);
+    mtm_sym(Gm, SG, Sp);
+    mtm_sym(X, X, XX);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Sp[i][j] += XX[i][j];
+  }
   // u = v - S b;  u' = u - W Z^{-1} V^T u;  v' = A^T u' + eta
   T u[N];
   mv(S, f.b, u);
@@ -291,17 +311,7 @@ MS_DEV void info_step(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>
     for (int j = 0; j < N; ++j) Sn[i][j] = Sp[i][j] + f.J[i][j];
   }
   if constexpr (kTraj) {
-    // G = A - V Z^{-1} (W^T A)
-    T X[NW][N];
-    mtm(W, f.A, X);
-    trsm_lower(Lz, dz, X);
-    trsm_upper_t(Lz, dz, X);
-    T VX[N][N];
-    mm(f.V, X, VX);
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) G[i][j] = f.A[i][j] - VX[i][j];
+    mcopy(Gm, G);
     // beta = (b + V V^T v) - V Z^{-1} W^T (b + V V^T v)
     T bc[N];
     {
@@ -397,7 +407,7 @@ MS_DEV void carry_apply(T (&S)[N][N], T (&v)[N], const Elem<T, N>& L) {
   T MSA[N][N];
   mm(MS_, L.A, MSA);
   T Sn[N][N];
-  mtm_sym(L.A, MSA, Sn);
+  mtm_symavg(L.A, MSA, Sn);
   T u[N];
   mv(S, L.b, u);
 #pragma unroll
@@ -495,7 +505,7 @@ MS_DEV void traj_step(const T (&G)[N][N], const T (&beta)[N], const T (&Lam)[N][
 // hence, with A_f = I - dt F, b_f = -dt c, C_f = V V^T,
 //   A   = A_f (A_s - K Y^{-1} H A_s)
 //   b   = A_f (u - K Y^{-1} H u) + b_f,      u = b_s + K D e
-//   C   = A_f (C_s - K Y^{-1} K^T) A_f^T + V V^T
+//   C   = A_f (C_s - K Y^{-1} K^T) A_f^T + V V^T   (the bracket in Joseph form)
 //   eta = (H A_s)^T Y^{-1} (e - H b_s) + eta_s
 //   J   = (H A_s)^T Y^{-1} (H A_s) + J_s.
 template <typename T, int N, int NY, int NW>
@@ -553,19 +563,33 @@ MS_DEV void prepend_step(const Step<T, N, NY, NW>& st, const T (&y)[NY], Elem<T,
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = 0; j < N; ++j) MA[i][j] = s.A[i][j] - KX[i][j];
-  // C: C_s - (Ly^{-1} K^T)^T (Ly^{-1} K^T)
-  T Yk[NY][N];
+  // C: M C_s = C_s - K Y^{-1} K^T in Joseph form Pi C_s Pi^T + Kg (R/dt) Kg^T
+  // with Kg = K Y^{-1}, Pi = I - Kg H (a sum of PSD terms: no cancellation
+  // where C_s is ill-conditioned)
+  T Kgt[NY][N];  // Kg^T = Y^{-1} K^T
 #pragma unroll
   for (int a = 0; a < NY; ++a)
 #pragma unroll
-    for (int i = 0; i < N; ++i) Yk[a][i] = K[i][a];
-  trsm_lower(Ly, dy, Yk);
-  T KYK[N][N], MC[N][N];
-  mtm_sym(Yk, Yk, KYK);
+    for (int i = 0; i < N; ++i) Kgt[a][i] = K[i][a];
+  trsm_lower(Ly, dy, Kgt);
+  trsm_upper_t(Ly, dy, Kgt);
+  T Pi[N][N], MC[N][N];
+  mtm(Kgt, st.H, Pi);
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) MC[i][j] = s.C[i][j] - KYK[i][j];
+    for (int j = 0; j < N; ++j) Pi[i][j] = (i == j ? T(1) : T(0)) - Pi[i][j];
+  {
+    T PC[N][N], RK[NY][N], KRK[N][N];
+    mm(Pi, s.C, PC);
+    mmt_sym(PC, Pi, MC);
+    mm(st.R, Kgt, RK);
+    mtm_sym(Kgt, RK, KRK);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) MC[i][j] = fma_(KRK[i][j], rdt, MC[i][j]);
+  }
   // outer factor A_f = I - dt F:  A_f X = X - dt F X
   T FX[N][N], FMC[N][N], Fm[N];
   mm(st.F, MA, FX);
@@ -626,7 +650,7 @@ MS_DEV void two_filter_point(const T (&S)[N][N], const T (&v)[N], const Elem<T, 
   mv(Mi, u, beta);
   T SG[N][N], Sh[N][N];
   mm(S, G, SG);
-  mtm_sym(s.A, SG, Sh);
+  mtm_symavg(s.A, SG, Sh);
   T Sb[N], w[N], vh[N];
   mv(S, beta, Sb);
 #pragma unroll
@@ -648,7 +672,7 @@ MS_DEV void two_filter_point(const T (&S)[N][N], const T (&v)[N], const Elem<T, 
   for (int i = 0; i < N; ++i) x[i] = beta[i] + Gz[i];
   if constexpr (kCov) {
     T Lam[N][N];
-    mmt_sym(Mi, s.C, Lam);  // (I + C S)^{-1} C, symmetric
+    mmt_symavg(Mi, s.C, Lam);  // (I + C S)^{-1} C, symmetric in exact arithmetic
     T Yg[N][N];
 #pragma unroll
     for (int i = 0; i < N; ++i)

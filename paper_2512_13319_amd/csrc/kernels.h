@@ -568,8 +568,14 @@ struct Cursor {
   };
   MS_DEVONLY void fetch(const Prob<TS>& p, int64_t i, Raw& r) const {
     r.dt = p.dt_stride ? p.dt[tix(i, 0, 1)] : p.dt[0];
+    if constexpr (M::kPadded) {
+      // measurements beyond the problem's ny are padding (zero)
 #pragma unroll
-    for (int c = 0; c < NY; ++c) r.y[c] = p.y[tix(i, c, NY)];
+      for (int c = 0; c < NY; ++c) r.y[c] = c < p.ny_in ? p.y[tix(i, c, p.ny_in)] : TS(0);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NY; ++c) r.y[c] = p.y[tix(i, c, NY)];
+    }
     if constexpr (M::kNonlinear) {
 #pragma unroll
       for (int c = 0; c < NX; ++c) r.xb[c] = p.xbar[tix(i, c, NX)];
@@ -712,6 +718,16 @@ struct Cursor {
     }
     psd_factor(blk.C, f.V);
   }
+  // ModelLinearPadded: each padded measurement component adds
+  // -1/2 (log 2 pi - log dt) to the prediction-error log-likelihood of a step
+  // (innovation 0, variance 1/dt, uncorrelated with the rest); this removes it
+  MS_DEVONLY double loglik_pad(const Step<T, NX, NY, NW>& st, const Prob<TS>& p) const {
+    if constexpr (M::kPadded) {
+      return 0.5 * double(NY - p.ny_in) * (1.8378770664093453 - ::log(double(st.dt)));
+    } else {
+      return 0.0;
+    }
+  }
   // divergence of the drift of a step (its terms st) at x, for the objective
   MS_DEVONLY T divergence(const Step<T, NX, NY, NW>& st, const T (&x)[NX]) const {
     if constexpr (M::NTH > 0) {
@@ -773,28 +789,36 @@ struct Cursor {
         st.c[a] = c[a];
       }
       T Wm[NW][NW], Lw[NW][NW], dw[NW], Lm[NX][NW];
+      // the problem's noise dimension (ModelLinearPadded: padded to NW with
+      // zero columns of L and W = I there)
+      const int nw = M::kPadded ? p.nw_in : NW;
 #pragma unroll
       for (int a = 0; a < NW; ++a)
 #pragma unroll
-        for (int b = 0; b < NW; ++b) Wm[a][b] = W[a * NW + b];
+        for (int b = 0; b < NW; ++b)
+          Wm[a][b] = (a < nw && b < nw) ? T(W[a * nw + b]) : (a == b ? T(1) : T(0));
       chol(Wm, Lw, dw);
 #pragma unroll
       for (int a = 0; a < NX; ++a)
 #pragma unroll
-        for (int b = 0; b < NW; ++b) Lm[a][b] = L[a * NW + b];
+        for (int b = 0; b < NW; ++b) Lm[a][b] = b < nw ? T(L[a * nw + b]) : T(0);
       mm(Lm, Lw, st.V);
       const T sd = sqrt_(dt);
 #pragma unroll
       for (int a = 0; a < NX; ++a)
 #pragma unroll
         for (int b = 0; b < NW; ++b) st.V[a][b] *= sd;
+      // the problem's measurement dimension (ModelLinearPadded: padded to NY
+      // with zero rows of H, r = 0 and R = I there)
+      const int ny = M::kPadded ? p.ny_in : NY;
 #pragma unroll
       for (int a = 0; a < NY; ++a) {
 #pragma unroll
-        for (int b = 0; b < NX; ++b) st.H[a][b] = H[a * NX + b];
-        st.r[a] = r[a];
+        for (int b = 0; b < NX; ++b) st.H[a][b] = a < ny ? T(H[a * NX + b]) : T(0);
+        st.r[a] = a < ny ? T(r[a]) : T(0);
 #pragma unroll
-        for (int b = 0; b < NY; ++b) st.R[a][b] = R[a * NY + b];
+        for (int b = 0; b < NY; ++b)
+          st.R[a][b] = (a < ny && b < ny) ? T(R[a * ny + b]) : (a == b ? T(1) : T(0));
       }
       spd_inv(st.R, st.Rinv);
     }
@@ -1565,7 +1589,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, Fi
             T vp[N];
 #pragma unroll
             for (int r = 0; r < N; ++r) vp[r] = vn[r] - f.eta[r];
-            ll += pred_loglik(Sp, vp, st, y);
+            ll += pred_loglik(Sp, vp, st, y) + cur.loglik_pad(st, p);
           }
           mcopy(Sn, S);
 #pragma unroll
@@ -1880,18 +1904,31 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
       if (p.om_div) ob += 0.5 * double(st.dt) * double(cur.divergence(st, xn));
       val[0] += ob;
       if constexpr (kGrad && M::NTH > 0) {
-        // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T
-        T Yw[NW][N], Nm[N][N];
+        // Nm = (I + S C)^{-1} S = S - W Z^{-1} W^T, in Joseph form
+        // Pi S Pi^T + K K^T with K = W Z^{-1}, Pi^T = I - V K^T (no
+        // cancellation where S is ill-conditioned)
+        T Kt[NW][N], Pt[N][N], Nm[N][N];
 #pragma unroll
         for (int a = 0; a < NW; ++a)
 #pragma unroll
-          for (int b = 0; b < N; ++b) Yw[a][b] = W[b][a];
-        trsm_lower(Lz, dz, Yw);
-        mtm_sym(Yw, Yw, Nm);
+          for (int b = 0; b < N; ++b) Kt[a][b] = W[b][a];
+        trsm_lower(Lz, dz, Kt);
+        trsm_upper_t(Lz, dz, Kt);
+        mm(f.V, Kt, Pt);
 #pragma unroll
         for (int a = 0; a < N; ++a)
 #pragma unroll
-          for (int b = 0; b < N; ++b) Nm[a][b] = S[a][b] - Nm[a][b];
+          for (int b = 0; b < N; ++b) Pt[a][b] = (a == b ? T(1) : T(0)) - Pt[a][b];
+        {
+          T SPt[N][N], KK[N][N];
+          mm(S, Pt, SPt);
+          mtm_sym(Pt, SPt, Nm);
+          mtm_sym(Kt, Kt, KK);
+#pragma unroll
+          for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) Nm[a][b] += KK[a][b];
+        }
         T NA[N][N], NAP[N][N], E2[N][N];
         mm(Nm, f.A, NA);
         mm(NA, Pn, NAP);

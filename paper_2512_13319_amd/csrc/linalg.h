@@ -173,6 +173,51 @@ MS_DEV void mtm_sym(const T (&a)[K][N], const T (&b)[K][N], T (&c)[N][N]) {
     }
 }
 
+// c = (a b^T + b a^T) / 2 and c = (a^T b + b^T a) / 2: products that are
+// symmetric only in exact arithmetic because one factor holds an inverse
+// (A_E (I + C J)^{-1} C A_E^T and the like).  The inverse's rounding has an
+// antisymmetric part that can exceed the product itself where the inverted
+// matrix is ill-conditioned; one triangle alone keeps it, the average drops
+// it.  Cost: the full N x N product.
+template <typename T, int N, int K>
+MS_DEV void mmt_symavg(const T (&a)[N][K], const T (&b)[N][K], T (&c)[N][N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      T s = a[i][0] * b[j][0];
+#pragma unroll
+      for (int l = 1; l < K; ++l) s = fma_(a[i][l], b[j][l], s);
+      if (j < i) {
+        T t = a[j][0] * b[i][0];
+#pragma unroll
+        for (int l = 1; l < K; ++l) t = fma_(a[j][l], b[i][l], t);
+        s = T(0.5) * (s + t);
+      }
+      c[i][j] = s;
+      c[j][i] = s;
+    }
+}
+template <typename T, int N, int K>
+MS_DEV void mtm_symavg(const T (&a)[K][N], const T (&b)[K][N], T (&c)[N][N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      T s = a[0][i] * b[0][j];
+#pragma unroll
+      for (int l = 1; l < K; ++l) s = fma_(a[l][i], b[l][j], s);
+      if (j < i) {
+        T t = a[0][j] * b[0][i];
+#pragma unroll
+        for (int l = 1; l < K; ++l) t = fma_(a[l][j], b[l][i], t);
+        s = T(0.5) * (s + t);
+      }
+      c[i][j] = s;
+      c[j][i] = s;
+    }
+}
+
 // y = a x
 template <typename T, int N, int K>
 MS_DEV void mv(const T (&a)[N][K], const T (&x)[K], T (&y)[N]) {

@@ -100,6 +100,25 @@ struct Entry {
   X(MAP_MODEL_LINEAR, 4, 4, 4, 0, ModelLinear<4 MS_COMMA 4 MS_COMMA 4>)
 #define MS_COMMA ,
 
+// General linear model for the (ny, nw) without an instantiation of their own:
+// ny, nw <= nx padded to nx (ModelLinearPadded).
+#define MS_PADDED_MODELS(X)                        \
+  X(1, ModelLinearPadded<1>)                       \
+  X(2, ModelLinearPadded<2>)                       \
+  X(3, ModelLinearPadded<3>)                       \
+  X(4, ModelLinearPadded<4>)                       \
+  X(5, ModelLinearPadded<5>)                       \
+  X(6, ModelLinearPadded<6>)                       \
+  X(7, ModelLinearPadded<7>)                       \
+  X(8, ModelLinearPadded<8>)
+
+bool padded_linear(const map_problem& p) {
+  return p.model == MAP_MODEL_LINEAR && p.nx >= 1 && p.nx <= 8 && p.ny >= 1 && p.ny <= p.nx &&
+         p.nw >= 1 && p.nw <= p.nx;
+}
+// general linear model above nx = 4: flat schedules and the RTS form only
+bool large_linear(const map_problem& p) { return p.model == MAP_MODEL_LINEAR && p.nx > 4; }
+
 // Models built with sub-stepped blocks (Blocked<M>, n_sub > 1).
 #define MS_BLOCKED_MODELS(X)                      \
   X(MAP_MODEL_CV, 4, 2, 2, 3, ModelCV<2>)         \
@@ -129,6 +148,17 @@ map_status dispatch(const map_problem& p, Fn&& f) {
   }
   MS_MODELS(MS_CASE)
 #undef MS_CASE
+  if (padded_linear(p)) {
+#define MS_PCASE(NX, M)                                                      \
+  if (p.nx == NX) {                                                          \
+    if (p.dtype == MAP_F64) return f.template run<double, double, M>();      \
+    if (p.dtype == MAP_F32) return f.template run<float, double, M>();       \
+    if constexpr (NX <= 4) return f.template run<float, float, M>();         \
+    return fail(MAP_E_UNSUPPORTED, "nx > 4 needs FP64 arithmetic (MAP_F64 or MAP_F32)"); \
+  }
+    MS_PADDED_MODELS(MS_PCASE)
+#undef MS_PCASE
+  }
   return fail(MAP_E_UNSUPPORTED, "model %d with (nx, ny, nw) = (%d, %d, %d) is not built", p.model,
               p.nx, p.ny, p.nw);
 }
@@ -138,6 +168,7 @@ int model_ntheta(const map_problem& p) {
   if (p.model == MODEL && p.nx == NX && p.ny == NY && p.nw == NW) return NTH;
   MS_MODELS(MS_NTH)
 #undef MS_NTH
+  if (padded_linear(p)) return 0;
   return -1;
 }
 
@@ -288,7 +319,8 @@ int resolve(const map_problem& p, bool allow_seg) {
     if (it != g_tuned.end()) c = it->second;
   }
   if (c == 0) c = heuristic(p);
-  if (c == kSchedSegWave && (!allow_seg || p.n_seg > int64_t(INT32_MAX))) c = heuristic(p);
+  if (c == kSchedSegWave && (!allow_seg || p.n_seg > int64_t(INT32_MAX) || large_linear(p)))
+    c = heuristic(p);
   return c;
 }
 
@@ -543,6 +575,9 @@ map_status map_two_filter_smooth(const map_problem* p, void* S, void* v, void* x
   if (p->flags & MAP_OM_DIVERGENCE)
     return fail(MAP_E_UNSUPPORTED, "map_two_filter_smooth: MAP_OM_DIVERGENCE is not supported");
   if ((s = check_blocks(*p, true, "map_two_filter_smooth")) != MAP_OK) return s;
+  if (large_linear(*p))
+    return fail(MAP_E_UNSUPPORTED, "map_two_filter_smooth: the general linear model is built up "
+                                   "to nx = 4 for the two-filter form");
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, nullptr, nullptr, nullptr, ws,
                static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
@@ -702,7 +737,8 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
   constexpr int kReps = 3;
   // the flat schedules, and for batches of many segments the segment-local one
   std::vector<int> cands(std::begin(kChunks), std::end(kChunks));
-  if (q.n_seg >= 64 && q.n_seg <= int64_t(INT32_MAX)) cands.push_back(kSchedSegWave);
+  if (q.n_seg >= 64 && q.n_seg <= int64_t(INT32_MAX) && !large_linear(q))
+    cands.push_back(kSchedSegWave);
   for (int c : cands) {
     q.chunk = c;
     SmoothArgs a{buf[0], buf[1], nullptr, nullptr, buf[2], buf[3], static_cast<double*>(buf[4]),

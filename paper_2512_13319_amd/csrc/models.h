@@ -48,6 +48,7 @@ struct Prob {
   const T* gx;             // [nx][n_states] cotangent of x* (the problem Ift<M> only)
   int om_div;              // MAP_OM_DIVERGENCE: the divergence term of eq. OM is included
   int n_sub;               // Euler substeps per grid step (Blocked<M> only; y holds ny * n_sub per state)
+  int ny_in, nw_in;        // the problem's ny, nw (ModelLinearPadded pads them to NX)
   // general linear model: row-major per-step matrices, stride 0 = shared by all steps
   const T *F, *c, *L, *W, *H, *r, *R;
   int64_t sF, sc, sL, sW, sH, sr, sR;
@@ -64,6 +65,7 @@ struct ModelCV {
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
+  static constexpr bool kPadded = false;   // see ModelLinearPadded below
   static constexpr int kAngle = -1;  // no angular measurement component
 
   template <typename T>
@@ -126,6 +128,7 @@ struct ModelVdP {
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
+  static constexpr bool kPadded = false;   // see ModelLinearPadded below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -193,6 +196,7 @@ struct ModelLorenz63 {
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
+  static constexpr bool kPadded = false;   // see ModelLinearPadded below
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -256,8 +260,20 @@ struct ModelLinear {
   static constexpr bool kAdjoint = false;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
+  static constexpr bool kPadded = false;   // see ModelLinearPadded below
   static constexpr int kAngle = -1;
   static constexpr bool kDivNewton = false;  // divergence trace F of the step (Cursor)
+};
+
+// General linear model of NX states whose measurement and noise dimensions
+// (ny, nw <= NX, Prob::ny_in, nw_in) are padded to NX when the terms are read:
+// H gets zero rows with r = 0 and R = I there, L zero columns with W = I
+// there.  The padding adds nothing to J, eta, C or the objective; its constant
+// in the prediction-error likelihood is removed (Cursor::loglik_pad).  One
+// instantiation per NX serves every (ny, nw) without one of its own.
+template <int NX_>
+struct ModelLinearPadded : ModelLinear<NX_, NX_, NX_> {
+  static constexpr bool kPadded = true;
 };
 
 // ------------------------------------------------------------------ coordinated turn
@@ -278,6 +294,7 @@ struct ModelCT {
   static constexpr bool kAdjoint = true;
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
+  static constexpr bool kPadded = false;   // see ModelLinearPadded below
   static constexpr int kAngle = 1;
   // divergence of the drift (eq. OM): zero (the turn rotates the velocity)
   static constexpr bool kDivNewton = false;

@@ -27,6 +27,8 @@ inline Prob<T> make_prob(const map_problem& q) {
   p.gx = nullptr;
   p.om_div = (q.flags & MAP_OM_DIVERGENCE) ? 1 : 0;
   p.n_sub = q.n_sub > 1 ? q.n_sub : 1;
+  p.ny_in = q.ny;
+  p.nw_in = q.nw;
   p.F = static_cast<const T*>(q.F);
   p.c = static_cast<const T*>(q.c);
   p.L = static_cast<const T*>(q.L);
@@ -241,9 +243,17 @@ hipError_t smooth_seg_wave(const map_problem& q, const SmoothArgs& a) {
               : launch_seg_wave<TS, T, M, false, false>(p, o, a.stream);
 }
 
+// General linear models above nx = 4 (their matrices no longer fit in
+// registers; the kernels run from scratch memory): flat schedules and the RTS
+// form only, which keeps their compilation within bounds.
+template <class M>
+constexpr bool kLargeLinear = M::kPadded && M::NX > 4;
+
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
-  if (a.chunk == kSchedSegWave) return smooth_seg_wave<TS, T, M>(q, a);
+  if constexpr (!kLargeLinear<M>) {
+    if (a.chunk == kSchedSegWave) return smooth_seg_wave<TS, T, M>(q, a);
+  }
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
@@ -282,7 +292,7 @@ hipError_t Runner<TS, T, M>::dense(const map_problem& q, const void* S, const vo
 
 template <typename TS, typename T, class M>
 hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& a) {
-  if constexpr (M::kBlocked) {
+  if constexpr (M::kBlocked || kLargeLinear<M>) {
     return hipErrorInvalidValue;  // rejected by the entry point
   } else {
     Prob<TS> p = make_prob<TS>(q);
@@ -355,6 +365,9 @@ hipError_t Runner<TS, T, M>::ift(const map_problem& q, const SmoothArgs& a, cons
   template struct Runner<double, double, M>; \
   template struct Runner<float, double, M>;  \
   template struct Runner<float, float, M>;
+// general linear model padded to NX, NX > 4: FP64 arithmetic only, one
+// storage type per unit
+#define MS_INSTANTIATE_LARGE(TS, M) template struct Runner<TS, double, M>;
 // sub-stepped blocks: FP64 arithmetic only
 #define MS_INSTANTIATE_BLOCKED(M)            \
   template struct Runner<double, double, Blocked<M>>; \

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_wave(Prob<TS> p, SegOut o) {
               T vp[N];
 #pragma unroll
               for (int a = 0; a < N; ++a) vp[a] = vn[a] - f.eta[a];
-              ll += pred_loglik(Sp, vp, st, y);
+              ll += pred_loglik(Sp, vp, st, y) + cur.loglik_pad(st, p);
             }
             mcopy(Sn, S);
 #pragma unroll

@@ -324,3 +324,26 @@ def test_substep_blocks_are_validated(seg):
     q = good(seg)
     q.n_sub = 1
     assert lib.map_dense_output(ctypes.byref(q), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
+
+
+def test_general_linear_shapes_are_validated(seg):
+    """The general linear model takes nx <= 8 with ny, nw <= nx (padded where
+    no instantiation of its own exists); above nx = 4 it needs FP64 arithmetic
+    and has no two-filter form."""
+    lib = _lib.load()
+    p = good(seg)
+    p.model, p.n_theta = _lib.MODELS["linear"], 0
+    p.nx, p.ny, p.nw = 6, 2, 3
+    p.m0_stride, p.P0_stride = 6, 36
+    for k in ("F", "c", "L", "W", "H", "r", "R"):
+        setattr(p, k, FAKE)
+    assert lib.map_workspace_bytes(ctypes.byref(p)) > 0
+    p.dtype = _lib.MAP_F32_FAST
+    assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, FAKE,
+                          1 << 40, None) in (-7, -8)
+    p.dtype = _lib.MAP_F64
+    assert lib.map_two_filter_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE,
+                                     1 << 40, None) == -8
+    p.ny = 7   # more measurements than states: no padded form
+    assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
+                               None) == -8

@@ -287,14 +287,20 @@ def ct(n_seg=64, T=2 ** 14, dt=1e-3, sv=5e-4, sw=0.02, r=(5e-3, 1e-3),
 
 
 def linear_random(T=64, nx=3, ny=2, nw=2, dt=0.05, time_varying=True, n_seg=1,
-                  seed=11, name="linear_random") -> Workload:
+                  seed=11, name="linear_random", stable=False) -> Workload:
     """A general time-varying linear-affine model (Sec. 2.4, eq. linear-statespace)
     with c != 0 and r != 0, dense F, L, H: F_k = F0 + 0.3 sin(0.1 k) F1,
     c_k = c0 cos(0.05 k), H_k = H0 + 0.2 cos(0.07 k) H1, r_k = r0 (1 + 0.5 sin(0.03 k)).
     L, W, R are shared by all steps.  All segments have length T and share
-    the model; their data differ."""
+    the model; their data differ.  `stable` shifts F0 so that its eigenvalues
+    have real part at most -0.5 (a random F0 grows without bound otherwise,
+    more often the larger nx, and long segments then reach magnitudes where
+    rounding of the state, not the method, sets the error of the
+    log-likelihood)."""
     rng = _rng(seed)
     F0 = rng.standard_normal((nx, nx)) * 0.6 - 0.5 * np.eye(nx)
+    if stable:
+        F0 -= max(np.linalg.eigvals(F0).real.max() + 0.5, 0.0) * np.eye(nx)
     F1 = rng.standard_normal((nx, nx)) * 0.4
     c0 = rng.standard_normal(nx)
     H0 = rng.standard_normal((ny, nx))
