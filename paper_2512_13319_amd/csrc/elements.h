@@ -143,6 +143,67 @@ MS_DEV void combine(const Elem<T, N>& E, const Elem<T, N>& L, Elem<T, N>& out) {
   }
 }
 
+// L <- E . L in place: the same arithmetic as combine(E, L, out), with the
+// earlier element E read field by field through `src` (get_J, get_eta,
+// get_A, get_b, get_C) when each is first needed, instead of being held whole.
+// Every field of E is read before the same field of L is overwritten, so E
+// may be another lane's L seen through a shuffle, in lockstep.  Live at the
+// peak: L, E's J, M, M A_L and M C_L (against E, L and the output for
+// combine).
+template <typename T, int N, class Src>
+MS_DEV void combine_into(const Src& src, Elem<T, N>& L) {
+  T JE[N][N], eE[N];
+  src.get_J(JE);
+  src.get_eta(eE);
+  T X[N][N], M[N][N];
+  mm(L.C, JE, X);
+#pragma unroll
+  for (int i = 0; i < N; ++i) X[i][i] += T(1);
+  inv(X, M);
+  T MA[N][N], MC[N][N];
+  mm(M, L.A, MA);  // M A_L
+  mm(M, L.C, MC);  // M C_L (symmetric in exact arithmetic)
+  T u[N], Mu[N];
+  mv(L.C, eE, u);
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] += L.b[i];
+  mv(M, u, Mu);
+  T w[N], Mw[N], s[N];
+  mv(JE, L.b, w);
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = eE[i] - w[i];
+  mtv(M, w, Mw);
+  mtv(L.A, Mw, s);
+  {
+    T JMA[N][N], Jn[N][N];
+    mm(JE, MA, JMA);
+    mtm_symavg(L.A, JMA, Jn);  // A_L^T M^T J_E A_L
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      L.eta[i] = s[i] + L.eta[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) L.J[i][j] = Jn[i][j] + L.J[i][j];
+    }
+  }
+  T EA[N][N], eb[N];
+  src.get_A(EA);
+  src.get_b(eb);
+  T t[N];
+  mv(EA, Mu, t);
+  T EC[N][N];
+  src.get_C(EC);
+  T AMC[N][N], Cn[N][N];
+  mm(EA, MC, AMC);
+  mmt_symavg(AMC, EA, Cn);  // A_E M C_L A_E^T
+  mm(EA, MA, L.A);          // A_E M A_L
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    L.b[i] = t[i] + eb[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) L.C[i][j] = Cn[i][j] + EC[i][j];
+  }
+}
+
 // agg <- agg . f  (fold a fresh element onto the right of a run).
 // With W = J_E V, Z = I + V^T W (SPD), M = I - V Z^{-1} W^T, M C_L = V Z^{-1} V^T,
 // and X = Z^{-1} W^T A_L: M A_L = A_L - V X, A_L^T M^T J_E A_L = (M A_L)^T J_E (M A_L) + X^T X.
@@ -393,34 +454,69 @@ MS_DEV void traj_map(const T (&S)[N][N], const T (&v)[N], const Fresh<T, N, NW>&
   mtm_sym(Yv, Yv, Lam);
 }
 
-// Carry application (S, v) . agg for a general run agg: only (J, eta) of the
-// result are needed.  S = 0 (no information yet) is allowed.
+// An element held whole (in registers), as a source for combine_into and
+// carry_apply.
 template <typename T, int N>
-MS_DEV void carry_apply(T (&S)[N][N], T (&v)[N], const Elem<T, N>& L) {
+struct RegSrc {
+  const Elem<T, N>& e;
+  MS_DEV void get_A(T (&a)[N][N]) const { mcopy(e.A, a); }
+  MS_DEV void get_b(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = e.b[r];
+  }
+  MS_DEV void get_eta(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = e.eta[r];
+  }
+  MS_DEV void get_C(T (&a)[N][N]) const { mcopy(e.C, a); }
+  MS_DEV void get_J(T (&a)[N][N]) const { mcopy(e.J, a); }
+};
+
+// Carry application (S, v) . agg for a general run agg: only (J, eta) of the
+// result are needed.  S = 0 (no information yet) is allowed.  The run is read
+// field by field through `src` (see combine_into).
+template <typename T, int N, class Src>
+MS_DEV void carry_apply_src(T (&S)[N][N], T (&v)[N], const Src& src) {
   T X[N][N], M[N][N];
-  mm(S, L.C, X);  // I + S C_L  (= I + J_E C_L with E the carry)
+  {
+    T LC[N][N];
+    src.get_C(LC);
+    mm(S, LC, X);  // I + S C_L  (= I + J_E C_L with E the carry)
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) X[i][i] += T(1);
   inv(X, M);
   T MS_[N][N];
-  mm(M, S, MS_);  // (I + S C)^{-1} S, symmetric
-  T MSA[N][N];
-  mm(MS_, L.A, MSA);
+  mm(M, S, MS_);  // (I + S C)^{-1} S, symmetric in exact arithmetic
+  T LA[N][N];
+  src.get_A(LA);
   T Sn[N][N];
-  mtm_symavg(L.A, MSA, Sn);
-  T u[N];
-  mv(S, L.b, u);
+  {
+    T MSA[N][N];
+    mm(MS_, LA, MSA);
+    mtm_symavg(LA, MSA, Sn);
+  }
+  T Lb[N], u[N];
+  src.get_b(Lb);
+  mv(S, Lb, u);
 #pragma unroll
   for (int i = 0; i < N; ++i) u[i] = v[i] - u[i];
   T Mu[N], an[N];
   mv(M, u, Mu);
-  mtv(L.A, Mu, an);
+  mtv(LA, Mu, an);
+  T Le[N], LJ[N][N];
+  src.get_eta(Le);
+  src.get_J(LJ);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    v[i] = an[i] + L.eta[i];
+    v[i] = an[i] + Le[i];
 #pragma unroll
-    for (int j = 0; j < N; ++j) S[i][j] = Sn[i][j] + L.J[i][j];
+    for (int j = 0; j < N; ++j) S[i][j] = Sn[i][j] + LJ[i][j];
   }
+}
+template <typename T, int N>
+MS_DEV void carry_apply(T (&S)[N][N], T (&v)[N], const Elem<T, N>& L) {
+  carry_apply_src(S, v, RegSrc<T, N>{L});
 }
 
 // ------------------------------------------------------------------ trajectory maps

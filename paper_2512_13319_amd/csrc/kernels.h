@@ -366,6 +366,84 @@ MS_DEVONLY void shfl_elem(Elem<T, N>& o, const Elem<T, N>& e, int src) {
   shfl_vec(o.eta, e.eta, src);
   shfl_sym(o.J, e.J, src);
 }
+// Sources of the earlier element for combine_into.
+// ShflSrc: lane `src`'s element e through shuffles, or the identity element
+// where !act (combining with the identity changes nothing, exactly).  Every
+// lane of the wavefront must run the combination, as each shuffle reads all
+// lanes.
+template <typename T, int N>
+struct ShflSrc {
+  const Elem<T, N>& e;
+  int src;
+  bool act;
+  MS_DEVONLY void get_A(T (&a)[N][N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        const T x = shfl(e.A[r][q], src);
+        a[r][q] = act ? x : (r == q ? T(1) : T(0));
+      }
+  }
+  MS_DEVONLY void get_b(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const T x = shfl(e.b[r], src);
+      b[r] = act ? x : T(0);
+    }
+  }
+  MS_DEVONLY void get_eta(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const T x = shfl(e.eta[r], src);
+      b[r] = act ? x : T(0);
+    }
+  }
+  MS_DEVONLY void sym(const T (&m)[N][N], T (&a)[N][N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) {
+        const T x = shfl(m[r][q], src);
+        a[r][q] = act ? x : T(0);
+        a[q][r] = a[r][q];
+      }
+  }
+  MS_DEVONLY void get_C(T (&a)[N][N]) const { sym(e.C, a); }
+  MS_DEVONLY void get_J(T (&a)[N][N]) const { sym(e.J, a); }
+};
+// PackedSrc: an element in the packed layout of pack_elem (LDS).
+template <typename T, int N>
+struct PackedSrc {
+  const T* w;
+  MS_DEVONLY void get_A(T (&a)[N][N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) a[r][q] = w[r * N + q];
+  }
+  MS_DEVONLY void get_b(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = w[N * N + r];
+  }
+  MS_DEVONLY void sym(int o, T (&a)[N][N]) const {
+    int c = o;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) {
+        a[r][q] = w[c++];
+        a[q][r] = a[r][q];
+      }
+  }
+  MS_DEVONLY void get_C(T (&a)[N][N]) const { sym(N * N + N, a); }
+  MS_DEVONLY void get_eta(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = w[N * N + N + Sym<N>::n + r];
+  }
+  MS_DEVONLY void get_J(T (&a)[N][N]) const { sym(N * N + 2 * N + Sym<N>::n, a); }
+};
+
 // element <-> ElemSz contiguous values (LDS staging)
 template <typename T, int N>
 MS_DEVONLY void pack_elem(T* w, const Elem<T, N>& e) {
@@ -1016,90 +1094,45 @@ MS_DEVONLY void release_counter(unsigned int* counters) {
 // four tiles, from the block aggregates (plane sets of nt items).
 template <typename T, int N>
 MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
+  // The run of one block only, but its registers size the whole kernel:
+  // elements are read field by field (combine_into, carry_apply_src) and no
+  // whole element is prefetched.
   __shared__ T s_w[4][ElemSz<N>::n];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
-  Elem<T, N> acc, tmp, o, nx_;
+  Elem<T, N> acc;
   if (t0 < t1) {
     load_elem(tile_agg, nt, t0, acc);
-    if (t0 + 1 < t1) load_elem(tile_agg, nt, t0 + 1, nx_);
     for (int64_t t = t0 + 1; t < t1; ++t) {
-      o = nx_;
-      if (t + 1 < t1) load_elem(tile_agg, nt, t + 1, nx_);  // one tile ahead
-      combine(acc, o, tmp);
-      acc = tmp;
+      Elem<T, N> o;
+      load_elem(tile_agg, nt, t, o);
+      combine_into(RegSrc<T, N>{acc}, o);
+      acc = o;
     }
   } else {
     elem_identity(acc);
   }
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
-  for (int d = 1; d < kWave; d <<= 1) {
-    shfl_elem(o, acc, lane >= d ? lane - d : lane);
-    if (lane >= d) {
-      combine(o, acc, tmp);
-      acc = tmp;
-    }
-  }
-  if (lane == kWave - 1) {
-    T* w = s_w[wv];
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q < N; ++q) w[c++] = acc.A[r][q];
-#pragma unroll
-    for (int r = 0; r < N; ++r) w[c++] = acc.b[r];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q <= r; ++q) w[c++] = acc.C[r][q];
-#pragma unroll
-    for (int r = 0; r < N; ++r) w[c++] = acc.eta[r];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q <= r; ++q) w[c++] = acc.J[r][q];
-  }
+  for (int d = 1; d < kWave; d <<= 1)
+    combine_into(ShflSrc<T, N>{acc, lane >= d ? lane - d : lane, lane >= d}, acc);
+  if (lane == kWave - 1) pack_elem(s_w[wv], acc);
   __syncthreads();
-  // exclusive prefix of the lane: waves before, then lanes before
-  Elem<T, N> lx;
-  shfl_elem(lx, acc, lane > 0 ? lane - 1 : 0);
-  if (lane == 0) elem_identity(lx);
+  // exclusive prefix of the lane: waves before, then lanes before (lane 0:
+  // the identity)
   T S[N][N], v[N];
   mzero(S);
 #pragma unroll
   for (int r = 0; r < N; ++r) v[r] = T(0);
-  for (int w = 0; w < wv; ++w) {
-    const T* s = s_w[w];
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q < N; ++q) o.A[r][q] = s[c++];
-#pragma unroll
-    for (int r = 0; r < N; ++r) o.b[r] = s[c++];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q <= r; ++q) { o.C[r][q] = s[c++]; o.C[q][r] = o.C[r][q]; }
-#pragma unroll
-    for (int r = 0; r < N; ++r) o.eta[r] = s[c++];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int q = 0; q <= r; ++q) { o.J[r][q] = s[c++]; o.J[q][r] = o.J[r][q]; }
-    carry_apply(S, v, o);
-  }
-  carry_apply(S, v, lx);
+  for (int w = 0; w < wv; ++w) carry_apply_src(S, v, PackedSrc<T, N>{s_w[w]});
+  carry_apply_src(S, v, ShflSrc<T, N>{acc, lane > 0 ? lane - 1 : 0, lane > 0});
   // carries before this thread's tiles (the one after its last tile is not needed)
-  if (t0 + 1 < t1) load_elem(tile_agg, nt, t0, nx_);
   for (int64_t t = t0; t < t1; ++t) {
     store_sym(tile_carry, nt, t, S, 0);
     store_vec(tile_carry, nt, t, v, Sym<N>::n);
     if (t + 1 < t1) {
-      o = nx_;
-      if (t + 2 < t1) load_elem(tile_agg, nt, t + 1, nx_);
+      Elem<T, N> o;
+      load_elem(tile_agg, nt, t, o);
       carry_apply(S, v, o);
     }
   }
@@ -1113,13 +1146,13 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws, int64_t nt) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
   const int64_t K = (nt + kBlock - 1) / kBlock;
   const int64_t t0 = min<int64_t>(tid * K, nt), t1 = min<int64_t>(t0 + K, nt);
-  Aff<T, N> acc, o, nx_;
+  // (run by one block, but its registers size the whole kernel: no map is
+  // prefetched)
+  Aff<T, N> acc, o;
   if (t0 < t1) {
     load_aff(ws.stile_agg, nt, t0, acc);
-    if (t0 + 1 < t1) load_aff(ws.stile_agg, nt, t0 + 1, nx_);
     for (int64_t t = t0 + 1; t < t1; ++t) {
-      o = nx_;
-      if (t + 1 < t1) load_aff(ws.stile_agg, nt, t + 1, nx_);  // one tile ahead
+      load_aff(ws.stile_agg, nt, t, o);
       aff_append(acc, o);
     }
   } else {
@@ -1171,13 +1204,11 @@ MS_DEVONLY void traj_tile_scan(const Ws<T>& ws, int64_t nt) {
   for (int r = 0; r < N; ++r) x[r] = ex.bt[r];
   mcopy(ex.Om, P);
   // values after this thread's tiles (the one before its first tile is not needed)
-  if (t1 - 1 > t0) load_aff(ws.stile_agg, nt, t1 - 1, nx_);
   for (int64_t t = t1 - 1; t >= t0; --t) {
     store_vec(ws.stile_carry, nt, t, x, 0);
     store_sym(ws.stile_carry, nt, t, P, N);
     if (t > t0) {
-      o = nx_;
-      if (t - 1 > t0) load_aff(ws.stile_agg, nt, t - 1, nx_);
+      load_aff(ws.stile_agg, nt, t, o);
       aff_apply(o, x, P);
     }
   }
@@ -1366,16 +1397,12 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
       if (h == 0 && jm < j1) lt_store_elem(ws.lane_half, g, agg);
     }
   }
-  // in-tile inclusive scan
-  Elem<T, N> o, tmp;
+  // in-tile inclusive scan (every lane combines; lanes below d with the
+  // identity, which leaves them unchanged)
+  Elem<T, N> o;
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
-  for (int d = 1; d < kWave; d <<= 1) {
-    shfl_elem(o, agg, lane >= d ? lane - d : lane);
-    if (lane >= d) {
-      combine(o, agg, tmp);
-      agg = tmp;
-    }
-  }
+  for (int d = 1; d < kWave; d <<= 1)
+    combine_into(ShflSrc<T, N>{agg, lane >= d ? lane - d : lane, lane >= d}, agg);
   shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
   if (lane == 0) elem_identity(o);
   // Lane prefixes are read only by the next kernel; written here, they drain
@@ -1393,25 +1420,22 @@ __global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc 
   Elem<T, N> pre;
   elem_identity(pre);
   if (wv == 1 || wv == 3) {
-    unpack_elem(s_blk[wv - 1], o);
-    unpack_elem(s_blk[wv], tmp);
-    combine(o, tmp, agg);  // x01 (wave 1), x23 (wave 3)
+    unpack_elem(s_blk[wv], agg);
+    combine_into(PackedSrc<T, N>{s_blk[wv - 1]}, agg);  // x01 (wave 1), x23 (wave 3)
     if (lane == 0) pack_elem(s_blk[4 + (wv >> 1)], agg);
   }
   __syncthreads();
   if (wv == 0) {
-    unpack_elem(s_blk[4], o);
-    unpack_elem(s_blk[5], tmp);
-    combine(o, tmp, agg);
+    unpack_elem(s_blk[5], agg);
+    combine_into(PackedSrc<T, N>{s_blk[4]}, agg);
     if (lane == 0) store_elem<T, N, true>(ws.tile_agg, gridDim.x, tile >> 2, agg);
   } else if (wv == 1) {
     unpack_elem(s_blk[0], pre);
   } else if (wv == 2) {
     unpack_elem(s_blk[4], pre);
   } else {
-    unpack_elem(s_blk[4], o);
-    unpack_elem(s_blk[2], tmp);
-    combine(o, tmp, pre);
+    unpack_elem(s_blk[2], pre);
+    combine_into(PackedSrc<T, N>{s_blk[4]}, pre);
   }
   const bool last = arrive_last(ws.counters + kCountersFilter);
   // tile prefixes: read only by the next kernel, written after the arrival
