@@ -1342,8 +1342,18 @@ MS_DEVONLY void zero_acc_grid(const Acc& a, int64_t n_seg, int64_t nth) {
   }
 }
 
-template <typename TS, typename T, class M>
-__global__ void __launch_bounds__(kBlock) k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
+// Two variants: kW = 2 asks the compiler for two wavefronts per SIMD (at
+// nx = 4 a spill of ~130 B a lane), kW = 1 for none (one wavefront, no
+// spill).  The launch takes the first when the grid has more wavefronts than
+// the chip has SIMDs, so that two can share one and hide each other's
+// latency; the second when every SIMD runs at most one.
+template <class M, int kW>
+struct UpWaves {
+  static constexpr int n = kW == 2 ? M::kWaves : 1;
+};
+template <typename TS, typename T, class M, int kW>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(UpWaves<M, kW>::n)))
+k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   constexpr int N = M::NX;
   __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
   const T* sstep = shared_step<TS, T, M>(p, s_step);
@@ -1499,8 +1509,16 @@ MS_DEVONLY double pred_loglik(const T (&Sp)[N][N], const T (&vp)[N], const Step<
   return -0.5 * (double(NY) * 1.8378770664093453 + 2.0 * ::log(det) + q);
 }
 
+// Two wavefronts per SIMD asked of the compiler (256 registers a lane) for
+// the models that fit without spilling (M::kWaves): the filter fix-up modes;
+// the two-filter mode would spill about 1 KB a lane and keeps one.
+template <class M, int kMode>
+struct DownWaves {
+  static constexpr int n = kMode != 3 ? M::kWaves : 1;
+};
 template <typename TS, typename T, class M, int kMode>
-__global__ void __launch_bounds__(kBlock) k_filter_down(Prob<TS> p, Ws<T> ws, FilterOut fo, Acc acc) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DownWaves<M, kMode>::n)))
+k_filter_down(Prob<TS> p, Ws<T> ws, FilterOut fo, Acc acc) {
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr bool kFilter = kMode != kModeTrajOnly;
   constexpr bool kTraj = kMode == kModeFused || kMode == kModeTrajOnly;

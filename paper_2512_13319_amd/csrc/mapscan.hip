@@ -732,35 +732,43 @@ map_status map_autotune(const map_problem* p, void* ws, size_t ws_bytes, const c
     cleanup();
     return fail(MAP_E_HIP, "map_autotune: hipEventCreate failed");
   }
-  int best = 0;
-  float best_ms = 0.f;
-  constexpr int kReps = 3;
+  constexpr int kReps = 3, kRounds = 2;
   // the flat schedules, and for batches of many segments the segment-local one
   std::vector<int> cands(std::begin(kChunks), std::end(kChunks));
   if (q.n_seg >= 64 && q.n_seg <= int64_t(INT32_MAX) && !large_linear(q))
     cands.push_back(kSchedSegWave);
-  for (int c : cands) {
-    q.chunk = c;
-    SmoothArgs a{buf[0], buf[1], nullptr, nullptr, buf[2], buf[3], static_cast<double*>(buf[4]),
-                 static_cast<double*>(buf[5]), static_cast<double*>(buf[6]),
-                 static_cast<double*>(buf[7]), ws, st, c};
-    s = dispatch(q, DoSmooth{q, a});  // warm-up
-    if (s == MAP_OK) s = hip_status(hipEventRecord(e0, st), "map_autotune");
-    for (int r = 0; r < kReps && s == MAP_OK; ++r) s = dispatch(q, DoSmooth{q, a});
-    if (s == MAP_OK) s = hip_status(hipEventRecord(e1, st), "map_autotune");
-    if (s == MAP_OK) s = hip_status(hipEventSynchronize(e1), "map_autotune");
-    float ms = 0.f;
-    if (s == MAP_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "map_autotune");
-    if (s != MAP_OK) {
-      cleanup();
-      return s;
+  // every candidate timed in each of kRounds interleaved rounds (warm-up in
+  // the first), its best round kept: schedules within ~10 % of each other
+  // otherwise swap places from run to run
+  std::vector<float> cand_ms(cands.size(), 0.f);
+  for (int round = 0; round < kRounds; ++round)
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      const int c = cands[ci];
+      q.chunk = c;
+      SmoothArgs a{buf[0], buf[1], nullptr, nullptr, buf[2], buf[3], static_cast<double*>(buf[4]),
+                   static_cast<double*>(buf[5]), static_cast<double*>(buf[6]),
+                   static_cast<double*>(buf[7]), ws, st, c};
+      if (round == 0) s = dispatch(q, DoSmooth{q, a});  // warm-up
+      if (s == MAP_OK) s = hip_status(hipEventRecord(e0, st), "map_autotune");
+      for (int r = 0; r < kReps && s == MAP_OK; ++r) s = dispatch(q, DoSmooth{q, a});
+      if (s == MAP_OK) s = hip_status(hipEventRecord(e1, st), "map_autotune");
+      if (s == MAP_OK) s = hip_status(hipEventSynchronize(e1), "map_autotune");
+      float ms = 0.f;
+      if (s == MAP_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "map_autotune");
+      if (s != MAP_OK) {
+        cleanup();
+        return s;
+      }
+      ms /= kReps;
+      if (round == 0 || ms < cand_ms[ci]) cand_ms[ci] = ms;
     }
-    ms /= kReps;
-    if (best == 0 || ms < best_ms) {
-      best = c;
-      best_ms = ms;
+  int best = 0;
+  float best_ms = 0.f;
+  for (size_t ci = 0; ci < cands.size(); ++ci)
+    if (best == 0 || cand_ms[ci] < best_ms) {
+      best = cands[ci];
+      best_ms = cand_ms[ci];
     }
-  }
   cleanup();
   {
     std::lock_guard<std::mutex> lk(sched::g_mu);

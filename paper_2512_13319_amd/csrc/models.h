@@ -66,6 +66,9 @@ struct ModelCV {
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr bool kPadded = false;   // see ModelLinearPadded below
+  // wavefronts per SIMD asked of the compiler for the filter passes (2: fits
+  // 256 registers a lane without spilling; see the kernels)
+  static constexpr int kWaves = 2;
   static constexpr int kAngle = -1;  // no angular measurement component
 
   template <typename T>
@@ -129,6 +132,9 @@ struct ModelVdP {
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr bool kPadded = false;   // see ModelLinearPadded below
+  // wavefronts per SIMD asked of the compiler for the filter passes (2: fits
+  // 256 registers a lane without spilling; see the kernels)
+  static constexpr int kWaves = 2;
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -197,6 +203,9 @@ struct ModelLorenz63 {
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr bool kPadded = false;   // see ModelLinearPadded below
+  // wavefronts per SIMD asked of the compiler for the filter passes (2: fits
+  // 256 registers a lane without spilling; see the kernels)
+  static constexpr int kWaves = 1;
   static constexpr int kAngle = -1;
 
   template <typename T>
@@ -261,6 +270,9 @@ struct ModelLinear {
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr bool kPadded = false;   // see ModelLinearPadded below
+  // wavefronts per SIMD asked of the compiler for the filter passes (2: fits
+  // 256 registers a lane without spilling; see the kernels)
+  static constexpr int kWaves = 1;
   static constexpr int kAngle = -1;
   static constexpr bool kDivNewton = false;  // divergence trace F of the step (Cursor)
 };
@@ -295,6 +307,9 @@ struct ModelCT {
   static constexpr bool kIft = false;  // see Ift below
   static constexpr bool kBlocked = false;  // see Blocked below
   static constexpr bool kPadded = false;   // see ModelLinearPadded below
+  // wavefronts per SIMD asked of the compiler for the filter passes (2: fits
+  // 256 registers a lane without spilling; see the kernels)
+  static constexpr int kWaves = 1;
   static constexpr int kAngle = 1;
   // divergence of the drift (eq. OM): zero (the turn rotates the velocity)
   static constexpr bool kDivNewton = false;
@@ -369,6 +384,7 @@ struct ModelCT {
 template <class M>
 struct Ift : M {
   static constexpr bool kIft = true;
+  static constexpr int kWaves = 1;  // its passes carry more state (would spill)
 };
 
 // ------------------------------------------------------------------ sub-stepped blocks
@@ -385,6 +401,7 @@ struct Blocked : M {
   static constexpr int NW = M::NX;
   static constexpr bool kAdjoint = false;
   static constexpr bool kBlocked = true;
+  static constexpr int kWaves = 1;  // the block state would spill at 256 registers
 
   template <typename T>
   static MS_DEV void terms(const T* th, const T (&x)[M::NX], T dt,

@@ -84,6 +84,35 @@ inline Ws<T> up_view(const Ws<T>& w) {
 
 inline unsigned grid_for(int64_t n_tiles) { return unsigned((n_tiles + 3) / 4); }
 
+// SIMDs of the current device (compute units x 4), read once per device.
+inline int64_t device_simds() {
+  static int64_t cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  if (cache[dev] == 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0)
+      cu = 256;
+    cache[dev] = int64_t(cu) * 4;
+  }
+  return cache[dev];
+}
+
+// The filter up-sweep, in the variant for the grid's wavefront count (see
+// k_filter_up).
+template <typename TS, typename T, class M>
+void launch_filter_up(unsigned grid, hipStream_t s, const Prob<TS>& p, const Ws<T>& w,
+                      const Acc& acc) {
+  if constexpr (M::kWaves == 2) {
+    if (int64_t(grid) * (kBlock / kWave) > device_simds()) {
+      k_filter_up<TS, T, M, 2><<<grid, kBlock, 0, s>>>(p, w, acc);
+      return;
+    }
+  }
+  k_filter_up<TS, T, M, 1><<<grid, kBlock, 0, s>>>(p, w, acc);
+}
+
 inline hipError_t zero(const Acc& a, int64_t n_seg, int64_t nth, hipStream_t st) {
   if (!a.loglik && !a.obj && !a.g_loglik && !a.g_obj) return hipSuccess;
   const int64_t n = n_seg * (nth > 1 ? nth : 1);
@@ -161,8 +190,8 @@ hipError_t Runner<TS, T, M>::filter(const map_problem& q, const SmoothArgs& a) {
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
-      p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
+  launch_filter_up<TS, T, M>(grid_for(w.n_tiles1), a.stream, p, up_view(w),
+      Acc{a.loglik, nullptr, nullptr, nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, a.m, a.P, a.loglik != nullptr};
@@ -259,8 +288,8 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);
-  k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
-      p, up_view(w), Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
+  launch_filter_up<TS, T, M>(grid_for(w.n_tiles1), a.stream, p, up_view(w),
+      Acc{a.loglik, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr});
   prof_end(kProfFilterUp, a.stream);
   MS_CHECK(hipGetLastError());
   FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
@@ -299,8 +328,8 @@ hipError_t Runner<TS, T, M>::two_filter(const map_problem& q, const SmoothArgs& 
     Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
     const unsigned g = grid_for(w.n_tiles);
     prof_begin(kProfFilterUp, a.stream);
-    k_filter_up<TS, T, M><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
-        p, up_view(w), Acc{a.loglik, nullptr, nullptr, nullptr});
+    launch_filter_up<TS, T, M>(grid_for(w.n_tiles1), a.stream, p, up_view(w),
+        Acc{a.loglik, nullptr, nullptr, nullptr});
     prof_end(kProfFilterUp, a.stream);
     MS_CHECK(hipGetLastError());
     FilterOut fo{a.S, a.v, nullptr, nullptr, a.loglik != nullptr};
@@ -335,8 +364,8 @@ hipError_t Runner<TS, T, M>::ift(const map_problem& q, const SmoothArgs& a, cons
     const unsigned g = grid_for(w.n_tiles);
     prof_begin(kProfIftSolve, a.stream);
     // also zeroes g_theta (the accumulator of the last kernel)
-    k_filter_up<TS, T, MI><<<grid_for(w.n_tiles1), kBlock, 0, a.stream>>>(
-        p, up_view(w), Acc{nullptr, nullptr, b.g_theta, nullptr});
+    launch_filter_up<TS, T, MI>(grid_for(w.n_tiles1), a.stream, p, up_view(w),
+        Acc{nullptr, nullptr, b.g_theta, nullptr});
     prof_end(kProfIftSolve, a.stream);
     MS_CHECK(hipGetLastError());
     FilterOut fo{a.S, b.vmu, nullptr, nullptr, 0};
