@@ -2060,7 +2060,9 @@ struct TrajOut {
   int want_grad;
 };
 
-template <typename TS, typename T, class M, bool kGrad, bool kCov>
+// kDepth: states prefetched ahead (rotating buffers); three keep the
+// registers within two wavefronts per SIMD.
+template <typename TS, typename T, class M, bool kGrad, bool kCov, int kDepth>
 __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, TrajOut to, Acc acc) {
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
@@ -2112,34 +2114,34 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
     cur.sstep = sstep;
     cur.init(p, il);
     seg_acc = cur.s;
-    // Filter moments of a state and inputs of the state after it, in three
+    // Filter moments of a state and inputs of the state after it, in kDepth
     // rotating buffers: this pass streams the most data, so each buffer is
     // refilled (always issued, clamped into the lane) at the end of the state
-    // that used it, for the state three steps further down, and its loads have
-    // two whole states to arrive.  Each buffer is read in place and refilled
-    // only after its last use, so the loop carries it in the same registers
-    // (a register copy of a buffer would make its loads wait early).
+    // that used it, for the state kDepth steps further down, and its loads have
+    // kDepth - 1 whole states to arrive.  Each buffer is read in place and
+    // refilled only after its last use, so the loop carries it in the same
+    // registers (a register copy of a buffer would make its loads wait early).
+    constexpr int K = kDepth;
     struct Ahead {
       TS S[Sym<N>::n];
       TS v[N];
       typename Cursor<TS, T, M>::Raw r;
-    } q0, q1, q2;
-    auto refill = [&](int64_t k, Ahead& q) {
+    } q[K];
+    auto refill = [&](int64_t k, Ahead& qq) {
       const int64_t ia = k >= j0 ? k : j0;
-      tload_raw(Si, Sym<N>::n, ia, q.S);
-      tload_raw(vi, N, ia, q.v);
-      cur.fetch(p, ia + 1 < ns ? ia + 1 : ia, q.r);
+      tload_raw(Si, Sym<N>::n, ia, qq.S);
+      tload_raw(vi, N, ia, qq.v);
+      cur.fetch(p, ia + 1 < ns ? ia + 1 : ia, qq.r);
     };
-    refill(il, q0);
-    refill(il - 1, q1);
-    refill(il - 2, q2);
-    // one state of the backward walk; q holds state i
-    auto body = [&](int64_t i, Ahead& q) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) refill(il - k, q[k]);
+    // one state of the backward walk; qq holds state i
+    auto body = [&](int64_t i, Ahead& qq) {
       T S[N][N], v[N];
-      sym_from_raw<TS, T, N>(q.S, S);
-      vec_from_raw(q.v, v);
+      sym_from_raw<TS, T, N>(qq.S, S);
+      vec_from_raw(qq.v, v);
       filter_plane_in<TS>(S, v);
-      const typename Cursor<TS, T, M>::Raw rc = q.r;
+      const typename Cursor<TS, T, M>::Raw rc = qq.r;
       traj_walk_state<TS, T, M, kGrad>(p, cur, i, S, v, rc, to.want_obj != 0, x, P, val);
       tstore_vec(xo, N, i, x);
       if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
@@ -2152,20 +2154,18 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
           seg_acc = cur.s;
         }
       }
-      refill(i - 3, q);
+      refill(i - K, qq);
     };
     drain_vmem();
     int64_t i = il;
-    for (; i - 2 >= j0; i -= 3) {
-      body(i, q0);
-      body(i - 1, q1);
-      body(i - 2, q2);
+    for (; i - (K - 1) >= j0; i -= K) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) body(i - k, q[k]);
     }
-    // the last one or two states (the rotation continues with q0, then q1)
-    for (; i >= j0; --i) {
-      body(i, q0);
-      q0 = q1;
-    }
+    // the last K - 1 states at most (the rotation continues with q[0], q[1], ...)
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k)
+      if (i - k >= j0) body(i - k, q[k]);
   }
   if (ws.status) {
 #pragma unroll

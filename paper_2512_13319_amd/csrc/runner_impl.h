@@ -158,6 +158,15 @@ hipError_t Runner<TS, T, M>::init_xbar(const map_problem& q, void* xbar, hipStre
   return hipGetLastError();
 }
 
+// Trajectory fix-up with three states prefetched (see k_traj_down; five,
+// for grids of at most one wavefront per SIMD, measured no faster at
+// T = 2^20: 58-59 against 50-57 us with the adjoint).
+template <typename TS, typename T, class M, bool kGrad, bool kCov>
+void launch_traj_depth(const Prob<TS>& p, const Ws<T>& w, const TrajOut& to, const Acc& acc,
+                       unsigned g, hipStream_t st) {
+  k_traj_down<TS, T, M, kGrad, kCov, 3><<<g, kBlock, 0, st>>>(p, w, to, acc);
+}
+
 // Trajectory fix-up, instantiated for (adjoint, covariance output).
 template <typename TS, typename T, class M>
 hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const Acc& acc, bool grad,
@@ -167,9 +176,9 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
     if (grad) {
       prof_begin(kProfTrajDownGrad, st);
       if (cov)
-        k_traj_down<TS, T, M, true, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+        launch_traj_depth<TS, T, M, true, true>(p, w, to, acc, g, st);
       else
-        k_traj_down<TS, T, M, true, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+        launch_traj_depth<TS, T, M, true, false>(p, w, to, acc, g, st);
       prof_end(kProfTrajDownGrad, st);
       return hipGetLastError();
     }
@@ -177,9 +186,9 @@ hipError_t launch_traj_down(const Prob<TS>& p, const Ws<T>& w, TrajOut to, const
   to.want_grad = 0;
   prof_begin(kProfTrajDown, st);
   if (cov)
-    k_traj_down<TS, T, M, false, true><<<g, kBlock, 0, st>>>(p, w, to, acc);
+    launch_traj_depth<TS, T, M, false, true>(p, w, to, acc, g, st);
   else
-    k_traj_down<TS, T, M, false, false><<<g, kBlock, 0, st>>>(p, w, to, acc);
+    launch_traj_depth<TS, T, M, false, false>(p, w, to, acc, g, st);
   prof_end(kProfTrajDown, st);
   return hipGetLastError();
 }
@@ -376,7 +385,7 @@ hipError_t Runner<TS, T, M>::ift(const map_problem& q, const SmoothArgs& a, cons
     MS_CHECK(hipGetLastError());
     TrajOut to{a.S, b.vmu, b.mu, nullptr, 0, 0};
     prof_begin(kProfIftSolve, a.stream);
-    k_traj_down<TS, T, MI, false, false><<<g, kBlock, 0, a.stream>>>(p, w, to, none);
+    k_traj_down<TS, T, MI, false, false, 3><<<g, kBlock, 0, a.stream>>>(p, w, to, none);
     prof_end(kProfIftSolve, a.stream);
     MS_CHECK(hipGetLastError());
     IftIn in{a.S, a.v, b.vmu, a.xs, b.mu};
