@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 7
+#define MAPSCAN_ABI_VERSION 8
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
 /* map_problem.flags: minimise the Onsager--Machlup objective with its
@@ -327,11 +327,23 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
  *                    per state) receives mu, vmu (out, tiled [nx] per state)
  *                    the adjoint problem's second filter plane; both must be
  *                    distinct from xs, S, v and g_xs.
+ *   g_elems          (debug output, or NULL) the per-step cotangents that
+ *                    the two gradients above are reduced from: at the state
+ *                    a step ends at (not at a segment's first state),
+ *                    tiled [2 E] doubles per state, E = nx*nx + nx +
+ *                    nx(nx+1)/2 + ny(ny+1)/2: d loglik / d(A, b, C, R) of
+ *                    the step's element (A = I - dt F, b = -dt c, C = dt Q,
+ *                    R the measurement density), then d obj / d(A, b, C, R);
+ *                    A row-major, C and R as the lower triangle (row order)
+ *                    of the gradient with respect to the full symmetric
+ *                    matrix.  Distinct from every other buffer.
  * For nonlinear models every gradient holds the linearisation point
- * p->xbar fixed.  At least one of g_loglik, g_obj, g_xs must be given. */
+ * p->xbar fixed.  At least one of g_loglik, g_obj, g_xs, g_elems must be
+ * given. */
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
-                        void* vmu, double* g_xs_theta, void* ws, size_t ws_bytes, void* stream);
+                        void* vmu, double* g_xs_theta, double* g_elems, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Schedule autotuner for the batched segmented scan.  Times the fused step
  * (map_smooth with every output, gradients for parametric models) at the

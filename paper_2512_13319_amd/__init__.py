@@ -432,13 +432,22 @@ def iterated_nonlinear(p: Problem, n_iter: int, xbar0=None, covariances=True, lo
                         g_obj=gm), natural)
 
 
+def elem_grad_size(p: Problem) -> int:
+    """Values per part of map_backward's per-step element cotangents:
+    A (nx*nx), b (nx), C (lower triangle) and R (lower triangle)."""
+    return p.nx * p.nx + p.nx + p.nsym + p.ny * (p.ny + 1) // 2
+
+
 def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, loglik_grad=True,
-             obj_grad=True, g_xs=None):
+             obj_grad=True, g_xs=None, elem_grads=False):
     """Adjoint from saved (tiled) filter planes S, v: recomputes the trajectory
     and returns d loglik / d theta and d obj / d theta per segment (when
     asked), and with `g_xs` (a cotangent of x*: natural [nx, n_states] or a
     tiled buffer) d(l)/d theta by the implicit function theorem (`g_xs_theta`)
-    together with mu = H^{-1} g_xs."""
+    together with mu = H^{-1} g_xs.  With `elem_grads`, also the per-step
+    element cotangents (`g_elems`: natural [2 E, n_states] doubles, E =
+    elem_grad_size(p): those of loglik then of obj, at the state each step
+    ends at; a segment's first state is zero)."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
@@ -454,11 +463,18 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, l
         mu = p._tiled(p.nx)
         vmu = p._tiled(p.nx)
         gxt = p._empty(p.n_seg, p.n_theta, dtype=f64)
+    ge = None
+    if elem_grads:
+        ge = torch.zeros(tiled_numel(p.n_states, 2 * elem_grad_size(p)), dtype=f64,
+                         device=p.device)
     _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
                                 _ptr(obj), _ptr(gl), _ptr(gm), _ptr(gx), _ptr(mu), _ptr(vmu),
-                                _ptr(gxt), _ptr(ws), ws.numel(), _stream()))
-    return _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm, mu=mu, g_xs_theta=gxt),
-                natural)
+                                _ptr(gxt), _ptr(ge), _ptr(ws), ws.numel(), _stream()))
+    r = _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm, mu=mu, g_xs_theta=gxt),
+             natural)
+    if ge is not None:
+        r["g_elems"] = from_tiled(ge, 2 * elem_grad_size(p), p.n_states) if natural else ge
+    return r
 
 
 class GraphedSmooth:

@@ -81,7 +81,7 @@ def load(path: str | None = None):
     lib.map_dense_output.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     lib.map_two_filter_smooth.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_iterated_nonlinear.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
-    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, vp, sz, vp]
+    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, dp, vp, sz, vp]
     lib.map_autotune.argtypes = [P, vp, sz, ctypes.c_char_p, ctypes.POINTER(i32), vp]
     lib.map_schedule.argtypes = [P, ctypes.POINTER(i32)]
     lib.map_lti_exact_terms.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]

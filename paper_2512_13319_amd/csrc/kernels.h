@@ -99,6 +99,10 @@ MS_DEVONLY void put(P* p, P v) {
 
 template <int N> struct Sym { static constexpr int n = N * (N + 1) / 2; };
 template <int N> struct ElemSz { static constexpr int n = N * N + 2 * N + 2 * Sym<N>::n; };
+// Per-step cotangents of (A, b, C, R): N * N + N + Sym<N> + Sym<NY> values.
+template <int N, int NY> struct ElemGradSz {
+  static constexpr int n = N * N + N + Sym<N>::n + Sym<NY>::n;
+};
 template <int N> struct AffSz { static constexpr int n = N * N + N + Sym<N>::n; };
 
 // --------------------------------------------------------------------------- SoA I/O
@@ -1860,7 +1864,8 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
                                 const T (&S)[M::NX][M::NX], const T (&v)[M::NX],
                                 const typename Cursor<TS, T, M>::Raw& rc, bool want_obj,
                                 T (&x)[M::NX], T (&P)[M::NX][M::NX],
-                                double (&val)[1 + 2 * (M::NTH > 0 ? M::NTH : 1)]) {
+                                double (&val)[1 + 2 * (M::NTH > 0 ? M::NTH : 1)],
+                                double* ge = nullptr) {
   constexpr int N = M::NX, NY = M::NY, NW = M::NW;
   constexpr int NTH = M::NTH > 0 ? M::NTH : 1;
   (void)NTH;
@@ -2019,6 +2024,34 @@ MS_DEVONLY void traj_walk_state(const Prob<TS>& p, const Cursor<TS, T, M>& cur, 
 #pragma unroll
           for (int a = 0; a < N; ++a) xb[a] = T(0);
         }
+        if (ge != nullptr) {
+          // the step's element cotangents, at the state it ends at: those of
+          // loglik, then those of the objective, each A (row-major), b, C
+          // (lower triangle, row order), R (lower triangle); C and R as the
+          // gradient with respect to the full symmetric matrix
+          constexpr int EG = ElemGradSz<N, NY>::n;
+          const int64_t j = i + 1;
+          int c = 0;
+          auto put2 = [&](T vl, T vm) {
+            ge[tix(j, c, 2 * EG)] = double(vl);
+            ge[tix(j, EG + c, 2 * EG)] = double(vm);
+            ++c;
+          };
+#pragma unroll
+          for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) put2(GAl[a][b], GAm[a][b]);
+#pragma unroll
+          for (int a = 0; a < N; ++a) put2(Gbl[a], Gbm[a]);
+#pragma unroll
+          for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) put2(GCl[a][b], GCm[a][b]);
+#pragma unroll
+          for (int a = 0; a < NY; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) put2(GRl[a][b], GRm[a][b]);
+        }
         double gl[NTH], gm[NTH];
 #pragma unroll
         for (int t = 0; t < NTH; ++t) gl[t] = gm[t] = 0.0;
@@ -2058,6 +2091,7 @@ struct TrajOut {
   void* Ps;   // optional [Sym][n_states]
   int want_obj;
   int want_grad;
+  double* g_elems;  // optional [2 ElemGradSz][n_states] (see traj_walk_state)
 };
 
 // kDepth: states prefetched ahead (rotating buffers); three keep the
@@ -2142,7 +2176,8 @@ __global__ void __launch_bounds__(kBlock) k_traj_down(Prob<TS> p, Ws<T> ws, Traj
       vec_from_raw(qq.v, v);
       filter_plane_in<TS>(S, v);
       const typename Cursor<TS, T, M>::Raw rc = qq.r;
-      traj_walk_state<TS, T, M, kGrad>(p, cur, i, S, v, rc, to.want_obj != 0, x, P, val);
+      traj_walk_state<TS, T, M, kGrad>(p, cur, i, S, v, rc, to.want_obj != 0, x, P, val,
+                                       to.g_elems);
       tstore_vec(xo, N, i, x);
       if constexpr (kCov) tstore_sym(Po, Sym<N>::n, i, P);
       if (ws.status) bad = bad | (kCov ? nonfinite_vd(x, P) : nonfinite_v(x));

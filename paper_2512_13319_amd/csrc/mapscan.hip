@@ -645,12 +645,18 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
 
 map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
-                        void* vmu, double* g_xs_theta, void* ws, size_t ws_bytes, void* stream) {
+                        void* vmu, double* g_xs_theta, double* g_elems, void* ws, size_t ws_bytes,
+                        void* stream) {
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
-  if (g_loglik == nullptr && g_obj == nullptr && g_xs == nullptr)
-    return fail(MAP_E_ARG, "nothing to differentiate: g_loglik, g_obj and g_xs are NULL");
+  if (g_loglik == nullptr && g_obj == nullptr && g_xs == nullptr && g_elems == nullptr)
+    return fail(MAP_E_ARG, "nothing to differentiate: g_loglik, g_obj, g_xs and g_elems are NULL");
+  if (g_elems != nullptr) {
+    const void* others[9] = {S, v, xs, Ps, obj, g_loglik, g_obj, g_xs, g_xs_theta};
+    for (const void* o : others)
+      if (o == g_elems) return fail(MAP_E_ARG, "g_elems aliases another buffer");
+  }
   if (g_xs != nullptr) {
     if (mu == nullptr || vmu == nullptr || g_xs_theta == nullptr)
       return fail(MAP_E_ARG, "g_xs needs mu, vmu and g_xs_theta");
@@ -667,8 +673,8 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
-               g_loglik, g_obj, ws, st, sched::resolve(*p, false)};
-  s = dispatch(*p, DoSmoother{*p, a, g_loglik != nullptr || g_obj != nullptr});
+               g_loglik, g_obj, ws, st, sched::resolve(*p, false), g_elems};
+  s = dispatch(*p, DoSmoother{*p, a, g_loglik != nullptr || g_obj != nullptr || g_elems != nullptr});
   if (s == MAP_OK && g_xs != nullptr)
     s = dispatch(*p, DoIft{*p, a, IftArgs{g_xs, mu, vmu, g_xs_theta}});
   return finish_check(*p, ws, st, s);

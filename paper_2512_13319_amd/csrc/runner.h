@@ -102,6 +102,7 @@ struct SmoothArgs {
   void* ws;
   hipStream_t stream;
   int chunk;  // states per lane (4, 8, 16 or 32)
+  double* g_elems = nullptr;  // map_backward: per-step element cotangents (flat schedules)
 };
 
 // Implicit-function VJP (map_backward with a cotangent of x*).

@@ -225,7 +225,7 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
   k_filter_down<TS, T, M, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfTrajUp, a.stream);
   MS_CHECK(hipGetLastError());
-  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
+  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad, grad ? a.g_elems : nullptr};
   return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 
@@ -307,7 +307,7 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   k_filter_down<TS, T, M, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
   prof_end(kProfFused, a.stream);
   MS_CHECK(hipGetLastError());
-  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad};
+  TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad, grad ? a.g_elems : nullptr};
   return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
 }
 

@@ -119,7 +119,7 @@ def test_flags_are_validated(seg):
     assert lib.map_two_filter_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE,
                                      1 << 40, None) == -8
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, None, None,
-                            None, None, None, FAKE, 1 << 40, None) == -8
+                            None, None, None, None, FAKE, 1 << 40, None) == -8
     assert b"MAP_OM_DIVERGENCE" in lib.map_last_error()
     assert "#define MAP_OM_DIVERGENCE %d" % _lib.MAP_OM_DIVERGENCE in open(HEADER).read()
     p.flags = 4
@@ -198,13 +198,18 @@ def test_workspace_and_output_checks(seg):
                                  None) == -1
     # nothing to differentiate
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, None,
-                            None, None, FAKE, 1 << 40, None) == -1
+                            None, None, None, FAKE, 1 << 40, None) == -1
     # a cotangent of x* needs mu, vmu and the output, none of them aliasing the inputs
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, FAKE, None,
-                            FAKE + 64, FAKE + 128, FAKE, 1 << 40, None) == -1
+                            FAKE + 64, FAKE + 128, None, FAKE, 1 << 40, None) == -1
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE + 8, FAKE + 16, None, None, None, None,
-                            FAKE + 24, FAKE + 16, FAKE + 32, FAKE + 40, FAKE, 1 << 40, None) == -1
+                            FAKE + 24, FAKE + 16, FAKE + 32, FAKE + 40, None, FAKE, 1 << 40,
+                            None) == -1
     assert b"distinct" in lib.map_last_error()
+    # per-step element cotangents must not alias another buffer
+    assert lib.map_backward(ctypes.byref(p), FAKE, FAKE + 8, FAKE + 16, None, None, None, None,
+                            None, None, None, None, FAKE + 16, FAKE, 1 << 40, None) == -1
+    assert b"g_elems aliases" in lib.map_last_error()
     assert lib.map_iterated_nonlinear(ctypes.byref(p), 0, None, FAKE, FAKE, FAKE, FAKE, None, None,
                                       None, None, None, FAKE, 1 << 40, None) == -1
     assert lib.map_iterated_nonlinear(ctypes.byref(p), 2, None, FAKE, FAKE, FAKE, FAKE, None, None,
@@ -225,7 +230,7 @@ def test_gradients_need_parametric_model():
     assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE, FAKE,
                           1 << 40, None) == -8
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, FAKE, None, None,
-                            None, None, FAKE, 1 << 40, None) == -8
+                            None, None, None, FAKE, 1 << 40, None) == -8
     p.R = None
     assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                None) == -1
