@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import workloads
-from oracle import cref
+from oracle import cref, ref
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +108,47 @@ def test_cfg4_full_batched_f32():
     print(f"cfg4 f32 ({len(segs)} sampled segments): xs {e_xs:.2e} Ps {e_Ps:.2e} "
           f"ll {e_ll:.2e} obj {e_ob:.2e}")
     assert max(e_xs, e_Ps, e_ll, e_ob) <= 1e-4
+
+
+def test_batched_f64_more_wavefronts_than_simds():
+    """600 ragged constant-velocity tracks (~1.9e6 steps) in FP64 at 16 states
+    per lane: the grid has more wavefronts than the chip has SIMDs, so the
+    filter up-sweep runs its two-wavefront variant (which no single 2^20-step
+    track reaches); the fused fix-up runs two wavefronts per SIMD at every
+    size.  Sampled segments against the oracle at 1e-9, gradients within the
+    per-component metric of tests/test_gpu_gradients.py."""
+    import paper_2512_13319_amd as ms
+    from tests.test_gpu_gradients import GTOL, grad_err
+    wl = workloads.cv_batched(n_seg=600, lmin=11.0, lmax=12.0, seed=41, gamma=0.1)
+    assert wl.n_steps + wl.n_seg > 1024 * 64 * 16  # more lanes than one wavefront per SIMD
+    lens = np.diff(wl.seg_off)
+    rng = np.random.default_rng(1)
+    segs = np.unique(np.concatenate([[np.argmin(lens), np.argmax(lens), 0, wl.n_seg - 1],
+                                     rng.choice(wl.n_seg, 12, replace=False)]))
+    sub, _ = sub_workload(wl, segs)
+    o = cref.smooth(sub)
+    p = ms.problem_from_workload(wl, dtype=torch.float64, chunk=16)
+    r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True)
+    torch.cuda.synchronize()
+    rows = state_rows(wl, segs)
+    e_xs = rel_err(r["xs"].cpu().numpy().T[rows], o["xs"])
+    e_Ps = rel_err(sym_full(ms, r["Ps"][:, torch.as_tensor(rows, device=r["Ps"].device)], 4),
+                   o["Ps"])
+    ll = r["loglik"].cpu().numpy()[segs]
+    ob = r["obj"].cpu().numpy()[segs]
+    e_ll = np.max(np.abs(ll - o["loglik"]) / np.abs(o["loglik"]))
+    e_ob = np.max(np.abs(ob - o["mstar"]) / np.abs(o["mstar"]))
+    print(f"batched f64 ({len(segs)} sampled segments): xs {e_xs:.2e} Ps {e_Ps:.2e} "
+          f"ll {e_ll:.2e} obj {e_ob:.2e}")
+    assert max(e_xs, e_Ps, e_ll, e_ob) <= 1e-9
+    # gradients of two sampled segments against oracle autograd
+    for s in segs[:2]:
+        seg = ref.workload_segment(wl, int(s))
+        T = seg["y"].shape[0]
+        gl, gm, _ = ref.gradients("cv", wl.nx, seg, torch.zeros(T + 1, wl.nx,
+                                                                   dtype=torch.float64))
+        for got, want in ((r["g_loglik"][s], gl), (r["g_obj"][s], gm)):
+            assert grad_err(got.cpu().numpy(), want.numpy()) <= GTOL["f64"], (s, got, want)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
