@@ -1128,7 +1128,14 @@ MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
   mzero(S);
 #pragma unroll
   for (int r = 0; r < N; ++r) v[r] = T(0);
-  for (int w = 0; w < wv; ++w) carry_apply_src(S, v, PackedSrc<T, N>{s_w[w]});
+  // applying a run to S = 0 gives its (J, eta) exactly: wave 0's total is
+  // taken as it is, the later ones applied
+  if (wv > 0) {
+    const PackedSrc<T, N> w0{s_w[0]};
+    w0.get_J(S);
+    w0.get_eta(v);
+  }
+  for (int w = 1; w < wv; ++w) carry_apply_src(S, v, PackedSrc<T, N>{s_w[w]});
   carry_apply_src(S, v, ShflSrc<T, N>{acc, lane > 0 ? lane - 1 : 0, lane > 0});
   // carries before this thread's tiles (the one after its last tile is not needed)
   for (int64_t t = t0; t < t1; ++t) {
