@@ -416,6 +416,38 @@ struct ShflSrc {
   MS_DEVONLY void get_C(T (&a)[N][N]) const { sym(e.C, a); }
   MS_DEVONLY void get_J(T (&a)[N][N]) const { sym(e.J, a); }
 };
+// BulkSrc: lane `src`'s element shuffled whole, in one burst, into registers
+// (the identity where !act); for kernels with registers to spare, where the
+// field-by-field shuffles of ShflSrc would only add latency.
+template <typename T, int N>
+struct BulkSrc {
+  Elem<T, N> e;
+  MS_DEVONLY BulkSrc(const Elem<T, N>& from, int src, bool act) {
+    shfl_elem(e, from, src);
+    if (!act) elem_identity(e);
+  }
+  MS_DEVONLY void get_A(T (&a)[N][N]) const { mcopy(e.A, a); }
+  MS_DEVONLY void get_b(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = e.b[r];
+  }
+  MS_DEVONLY void get_eta(T (&b)[N]) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) b[r] = e.eta[r];
+  }
+  MS_DEVONLY void get_C(T (&a)[N][N]) const { mcopy(e.C, a); }
+  MS_DEVONLY void get_J(T (&a)[N][N]) const { mcopy(e.J, a); }
+};
+// The source of a wavefront-scan partner: bulk where registers allow it.
+template <typename T, int N, bool kBulk>
+MS_DEVONLY void scan_step(Elem<T, N>& agg, int src, bool act) {
+  if constexpr (kBulk) {
+    combine_into(BulkSrc<T, N>(agg, src, act), agg);
+  } else {
+    combine_into(ShflSrc<T, N>{agg, src, act}, agg);
+  }
+}
+
 // PackedSrc: an element in the packed layout of pack_elem (LDS).
 template <typename T, int N>
 struct PackedSrc {
@@ -1096,7 +1128,7 @@ MS_DEVONLY void release_counter(unsigned int* counters) {
 
 // Filter block scan, run by the last block: (S, v) before every block of
 // four tiles, from the block aggregates (plane sets of nt items).
-template <typename T, int N>
+template <typename T, int N, bool kBulk>
 MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
   // The run of one block only, but its registers size the whole kernel:
   // elements are read field by field (combine_into, carry_apply_src) and no
@@ -1118,8 +1150,7 @@ MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
     elem_identity(acc);
   }
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
-  for (int d = 1; d < kWave; d <<= 1)
-    combine_into(ShflSrc<T, N>{acc, lane >= d ? lane - d : lane, lane >= d}, acc);
+  for (int d = 1; d < kWave; d <<= 1) scan_step<T, N, kBulk>(acc, lane >= d ? lane - d : lane, lane >= d);
   if (lane == kWave - 1) pack_elem(s_w[wv], acc);
   __syncthreads();
   // exclusive prefix of the lane: waves before, then lanes before (lane 0:
@@ -1135,8 +1166,19 @@ MS_DEVONLY void filter_tile_scan(const T* tile_agg, T* tile_carry, int64_t nt) {
     w0.get_J(S);
     w0.get_eta(v);
   }
-  for (int w = 1; w < wv; ++w) carry_apply_src(S, v, PackedSrc<T, N>{s_w[w]});
-  carry_apply_src(S, v, ShflSrc<T, N>{acc, lane > 0 ? lane - 1 : 0, lane > 0});
+  for (int w = 1; w < wv; ++w) {
+    if constexpr (kBulk) {
+      Elem<T, N> e;
+      unpack_elem(s_w[w], e);
+      carry_apply(S, v, e);
+    } else {
+      carry_apply_src(S, v, PackedSrc<T, N>{s_w[w]});
+    }
+  }
+  if constexpr (kBulk)
+    carry_apply_src(S, v, BulkSrc<T, N>(acc, lane > 0 ? lane - 1 : 0, lane > 0));
+  else
+    carry_apply_src(S, v, ShflSrc<T, N>{acc, lane > 0 ? lane - 1 : 0, lane > 0});
   // carries before this thread's tiles (the one after its last tile is not needed)
   for (int64_t t = t0; t < t1; ++t) {
     store_sym(tile_carry, nt, t, S, 0);
@@ -1366,6 +1408,9 @@ template <typename TS, typename T, class M, int kW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(UpWaves<M, kW>::n)))
 k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   constexpr int N = M::NX;
+  // one wavefront per SIMD of a model that fits two elsewhere: registers to
+  // spare for whole-element shuffles in the scans
+  constexpr bool kBulkUp = M::kWaves == 2 && kW == 1;
   __shared__ __align__(16) T s_step[SharedStep<T, M>::n];
   const T* sstep = shared_step<TS, T, M>(p, s_step);
   const int lane = threadIdx.x & (kWave - 1);
@@ -1422,8 +1467,7 @@ k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   // identity, which leaves them unchanged)
   Elem<T, N> o;
 #pragma unroll 1  // one copy of the level body: keeps the kernel inside the instruction cache
-  for (int d = 1; d < kWave; d <<= 1)
-    combine_into(ShflSrc<T, N>{agg, lane >= d ? lane - d : lane, lane >= d}, agg);
+  for (int d = 1; d < kWave; d <<= 1) scan_step<T, N, kBulkUp>(agg, lane >= d ? lane - d : lane, lane >= d);
   shfl_elem(o, agg, lane > 0 ? lane - 1 : 0);
   if (lane == 0) elem_identity(o);
   // Lane prefixes are read only by the next kernel; written here, they drain
@@ -1440,15 +1484,25 @@ k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
   __syncthreads();
   Elem<T, N> pre;
   elem_identity(pre);
+  // E . L with E from the packed LDS copy: read whole where registers allow
+  auto lds_step = [&](const T* w, Elem<T, N>& l) {
+    if constexpr (kBulkUp) {
+      Elem<T, N> e;
+      unpack_elem(w, e);
+      combine_into(RegSrc<T, N>{e}, l);
+    } else {
+      combine_into(PackedSrc<T, N>{w}, l);
+    }
+  };
   if (wv == 1 || wv == 3) {
     unpack_elem(s_blk[wv], agg);
-    combine_into(PackedSrc<T, N>{s_blk[wv - 1]}, agg);  // x01 (wave 1), x23 (wave 3)
+    lds_step(s_blk[wv - 1], agg);  // x01 (wave 1), x23 (wave 3)
     if (lane == 0) pack_elem(s_blk[4 + (wv >> 1)], agg);
   }
   __syncthreads();
   if (wv == 0) {
     unpack_elem(s_blk[5], agg);
-    combine_into(PackedSrc<T, N>{s_blk[4]}, agg);
+    lds_step(s_blk[4], agg);
     if (lane == 0) store_elem<T, N, true>(ws.tile_agg, gridDim.x, tile >> 2, agg);
   } else if (wv == 1) {
     unpack_elem(s_blk[0], pre);
@@ -1456,13 +1510,13 @@ k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
     unpack_elem(s_blk[4], pre);
   } else {
     unpack_elem(s_blk[2], pre);
-    combine_into(PackedSrc<T, N>{s_blk[4]}, pre);
+    lds_step(s_blk[4], pre);
   }
   const bool last = arrive_last(ws.counters + kCountersFilter);
   // tile prefixes: read only by the next kernel, written after the arrival
   if (lane == 0 && wv > 0 && tile < ws.n_tiles) store_elem(ws.tile_pre, ws.n_tiles, tile, pre);
   if (last) {
-    filter_tile_scan<T, N>(ws.tile_agg, ws.tile_carry, int64_t(gridDim.x));
+    filter_tile_scan<T, N, kBulkUp>(ws.tile_agg, ws.tile_carry, int64_t(gridDim.x));
     release_counter(ws.counters + kCountersFilter);
   }
 }
