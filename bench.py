@@ -166,6 +166,9 @@ def main():
                     help="use the library's default schedule instead of autotuning it")
     ap.add_argument("--no-two-filter", action="store_true",
                     help="skip the two-filter smoother measurement")
+    ap.add_argument("--no-checkpointed", action="store_true",
+                    help="skip the checkpointed training step (filter checkpoint, adjoint "
+                         "rebuilds S, v)")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the exact-discretisation (linear-model path) measurement")
     ap.add_argument("--ct-chunk", type=int, default=0,
@@ -288,6 +291,40 @@ def main():
                       "roofline": roofline_for(kern_tf, rec, fresh, p.n_states, p.nx, p.ny, s,
                                                args.dtype, chunk)}
 
+    checkpointed = None
+    if not args.no_checkpointed:
+        # the same training step with activation checkpointing: the forward
+        # call keeps only the filter's block carries, the adjoint rebuilds S, v
+        # from them (one more filter up-sweep without its cross-block step and
+        # one more fused fix-up) before the trajectory pass with the gradients
+        ck_out = dict(out)
+        ck_out["ckpt"] = torch.empty(ms.checkpoint_bytes(p), dtype=torch.uint8, device=dev)
+
+        def step_ck():
+            ms.smooth(p, covariances=False, loglik=True, objective=True, grad=False, out=ck_out,
+                      natural=False, checkpoint=True)
+            ms.backward(p, ck_out["S"], ck_out["v"], covariances=True, objective=True,
+                        natural=False, ckpt=ck_out["ckpt"], out=ck_out)
+
+        ms_ck_e, _, kern_ck = timed(step_ck, args.steps, args.warmup, True)
+        if args.no_graph:
+            ms_ck = ms_ck_e
+        else:
+            g_ck = ms.GraphedSmooth(p, covariances=True, loglik=True, objective=True, grad=True,
+                                    form="checkpointed")
+            ms_ck, _, _ = timed(g_ck.replay, args.steps, args.warmup, False)
+        planes = (nsym + p.nx) * s * p.n_states
+        checkpointed = {
+            "value": T / (ms_ck * 1e-3), "unit": "time-steps/s", "ms_per_step": ms_ck,
+            "eager_ms_per_step": round(ms_ck_e, 4),
+            "outputs": "as the headline step: x*, P^s, log-likelihood, objective, adjoint",
+            "kept_bytes": int(ck_out["ckpt"].numel()),
+            "kept_bytes_saved_planes": int(planes),
+            "kernels_ms": {k: round(v[1], 4) for k, v in kern_ck.items()},
+            "kernels_note": "averages pool the forward call's and the adjoint's launches of "
+                            "each kind (the adjoint's filter up-sweep skips the cross-block "
+                            "step)"}
+
     res = {
         "metric": METRIC,
         "value": T / (ms_fa * 1e-3),
@@ -315,6 +352,8 @@ def main():
     }
     if two_filter is not None:
         res["two_filter"] = two_filter
+    if checkpointed is not None:
+        res["checkpointed"] = checkpointed
 
     if args.copy_calibration:
         # plain device-to-device copy of a known size, read and written once,

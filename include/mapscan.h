@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define MAPSCAN_ABI_VERSION 8
+#define MAPSCAN_ABI_VERSION 9
 #define MAPSCAN_TILE 1024
 #define MAP_CHECK_FINITE 1
 /* map_problem.flags: minimise the Onsager--Machlup objective with its
@@ -259,6 +259,37 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
                               double* loglik, double* obj, double* g_loglik, double* g_obj,
                               void* stream);
 
+/* Filter checkpoints for the adjoint (activation checkpointing; not in the
+ * paper).  The filter scan's state at the start of every block of the scan's
+ * decomposition -- (S, v) before each run of 4 x 64 lanes x chunk states, the
+ * carries of the block-level scan of Sec. 3.4 eq. valueparallel -- is all that
+ * map_backward needs besides the inputs: from it, each block's lane and tile
+ * prefixes and then S, v at every state are rebuilt locally, with no
+ * cross-block step.  Between a forward call and its adjoint the caller then
+ * keeps (nx(nx+1)/2 + nx) values per block instead of per state (at chunk 16,
+ * one per 4096 states; 3.6 KB at nx = 4 and 2^20 steps, against 117 MB of
+ * S, v planes).
+ *
+ * map_checkpoint_bytes: bytes of that checkpoint for this problem (0 if the
+ * problem is invalid), at the flat schedule that map_backward resolves for it
+ * (p->chunk, else map_autotune's record, else the heuristic).  The forward call
+ * and the adjoint must resolve the same schedule: pin p->chunk (map_schedule)
+ * if map_autotune may run in between.  Values have the arithmetic type
+ * (double, float for MAP_F32_FAST). */
+size_t map_checkpoint_bytes(const map_problem* p);
+
+/* map_smooth on the flat schedule above that also writes the filter
+ * checkpoint to ckpt (device, map_checkpoint_bytes bytes, distinct from every
+ * other buffer and outside the workspace).  Same outputs, kernels and results
+ * as map_smooth on that schedule; the block carries are written straight to
+ * ckpt instead of the workspace.  S, v are still written (the trajectory pass
+ * reads them) and may be scratch the caller drops afterwards.  Parametric
+ * models only (the adjoint's domain); no sub-stepped blocks. */
+map_status map_smooth_checkpointed(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                                   double* loglik, double* obj, double* g_loglik, double* g_obj,
+                                   void* ckpt, size_t ckpt_bytes, void* ws, size_t ws_bytes,
+                                   void* stream);
+
 /* Two-filter smoother (Sec. 4.3, eq. twofilter): the same MAP trajectory as
  * map_smooth, recovered the paper's second way.  The filter scan gives the
  * forward value function (S_k, v_k); a reverse segmented scan with the same
@@ -309,8 +340,15 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
                                   void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint from saved filter moments.  Elements are recomputed from the
- * inputs (never stored); the filter's S and v planes (map_filter_scan or
- * map_smooth) are read.  Reverse-scans the same elements to rebuild xs and
+ * inputs (never stored).  With ckpt = NULL the filter's S and v planes
+ * (map_filter_scan or map_smooth) are read.  With a filter checkpoint of
+ * map_smooth_checkpointed on the same problem (ckpt, ckpt_bytes >=
+ * map_checkpoint_bytes), S and v are OUTPUTS instead: the filter planes are
+ * rebuilt from the checkpoint's block carries (one more filter up-sweep
+ * without its cross-block step, and the filter fix-up fused with the
+ * trajectory maps) and written there, distinct from each other and from every
+ * other buffer; the results equal those of the call with the saved planes.
+ * Reverse-scans the same elements to rebuild xs and
  * Ps (written to the caller's buffers) and accumulates, per segment
  * ([n_seg][n_theta] double, each optional):
  *   g_loglik, g_obj  d loglik / d theta (Fisher identity) and d obj / d theta
@@ -340,10 +378,10 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
  * For nonlinear models every gradient holds the linearisation point
  * p->xbar fixed.  At least one of g_loglik, g_obj, g_xs, g_elems must be
  * given. */
-map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+map_status map_backward(const map_problem* p, void* S, void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
-                        void* vmu, double* g_xs_theta, double* g_elems, void* ws, size_t ws_bytes,
-                        void* stream);
+                        void* vmu, double* g_xs_theta, double* g_elems, const void* ckpt,
+                        size_t ckpt_bytes, void* ws, size_t ws_bytes, void* stream);
 
 /* Schedule autotuner for the batched segmented scan.  Times the fused step
  * (map_smooth with every output, gradients for parametric models) at the

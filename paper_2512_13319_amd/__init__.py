@@ -338,10 +338,21 @@ def smoother_scan(p: Problem, S, v, covariances=True, objective=True, natural=Tr
     return _nat(p, dict(xs=xs, Ps=Ps, obj=obj), natural)
 
 
+def checkpoint_bytes(p: Problem) -> int:
+    """Bytes of the filter checkpoint map_smooth_checkpointed writes for `p`."""
+    n = int(_lib.load().map_checkpoint_bytes(ctypes.byref(p.struct)))
+    if n == 0:
+        _lib.check(-1)  # MAP_E_ARG, with the library's message
+    return n
+
+
 def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False, out=None,
-           natural=True):
+           natural=True, checkpoint=False):
     """Fused filter + trajectory scans (+ adjoint when grad).  `out` may carry
-    preallocated tiled buffers (same keys as the result) to avoid allocations."""
+    preallocated tiled buffers (same keys as the result) to avoid allocations.
+    With `checkpoint`, runs map_smooth_checkpointed: the result also holds the
+    filter checkpoint (`ckpt`, a byte tensor) that `backward(..., ckpt=...)`
+    rebuilds S, v from."""
     lib = _lib.load()
     ws = p.workspace()
     o = out or {}
@@ -359,11 +370,22 @@ def smooth(p: Problem, covariances=True, loglik=True, objective=True, grad=False
     if grad:
         gl = o.get("g_loglik") if o.get("g_loglik") is not None else p._empty(p.n_seg, p.n_theta, dtype=f64)
         gm = o.get("g_obj") if o.get("g_obj") is not None else p._empty(p.n_seg, p.n_theta, dtype=f64)
-    _lib.check(lib.map_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
-                              _ptr(ll), _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
-                              _stream()))
-    return _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm),
-                natural)
+    if checkpoint:
+        ck = o.get("ckpt") if o.get("ckpt") is not None else \
+            torch.empty(checkpoint_bytes(p), dtype=torch.uint8, device=p.device)
+        _lib.check(lib.map_smooth_checkpointed(
+            ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps), _ptr(ll), _ptr(obj),
+            _ptr(gl), _ptr(gm), _ptr(ck), ck.numel(), _ptr(ws), ws.numel(), _stream()))
+    else:
+        ck = None
+        _lib.check(lib.map_smooth(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
+                                  _ptr(ll), _ptr(obj), _ptr(gl), _ptr(gm), _ptr(ws), ws.numel(),
+                                  _stream()))
+    r = _nat(p, dict(S=S, v=v, xs=xs, Ps=Ps, loglik=ll, obj=obj, g_loglik=gl, g_obj=gm),
+             natural)
+    if ck is not None:
+        r["ckpt"] = ck
+    return r
 
 
 def two_filter_smooth(p: Problem, covariances=True, loglik=True, out=None, natural=True):
@@ -439,7 +461,7 @@ def elem_grad_size(p: Problem) -> int:
 
 
 def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, loglik_grad=True,
-             obj_grad=True, g_xs=None, elem_grads=False):
+             obj_grad=True, g_xs=None, elem_grads=False, ckpt=None, out=None):
     """Adjoint from saved (tiled) filter planes S, v: recomputes the trajectory
     and returns d loglik / d theta and d obj / d theta per segment (when
     asked), and with `g_xs` (a cotangent of x*: natural [nx, n_states] or a
@@ -447,15 +469,26 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, l
     together with mu = H^{-1} g_xs.  With `elem_grads`, also the per-step
     element cotangents (`g_elems`: natural [2 E, n_states] doubles, E =
     elem_grad_size(p): those of loglik then of obj, at the state each step
-    ends at; a segment's first state is zero)."""
+    ends at; a segment's first state is zero).  With `ckpt` (the filter
+    checkpoint of smooth(..., checkpoint=True)) S, v are rebuilt instead of
+    read: pass None for both (fresh buffers, returned as `S`, `v`) or tiled
+    buffers to write.  `out` may carry preallocated tiled buffers for xs, Ps,
+    obj, g_loglik and g_obj."""
     lib = _lib.load()
     ws = p.workspace()
     f64 = torch.float64
-    xs = p._tiled(p.nx)
-    Ps = p._tiled(p.nsym) if covariances else None
-    obj = p._empty(p.n_seg, dtype=f64) if objective else None
-    gl = p._empty(p.n_seg, p.n_theta, dtype=f64) if loglik_grad else None
-    gm = p._empty(p.n_seg, p.n_theta, dtype=f64) if obj_grad else None
+    if ckpt is not None:
+        S = p._tiled(p.nsym) if S is None else S
+        v = p._tiled(p.nx) if v is None else v
+    o = out or {}
+
+    def buf(key, make, want=True):
+        return (o[key] if o.get(key) is not None else make()) if want else None
+    xs = buf("xs", lambda: p._tiled(p.nx))
+    Ps = buf("Ps", lambda: p._tiled(p.nsym), covariances)
+    obj = buf("obj", lambda: p._empty(p.n_seg, dtype=f64), objective)
+    gl = buf("g_loglik", lambda: p._empty(p.n_seg, p.n_theta, dtype=f64), loglik_grad)
+    gm = buf("g_obj", lambda: p._empty(p.n_seg, p.n_theta, dtype=f64), obj_grad)
     gx = mu = vmu = gxt = None
     if g_xs is not None:
         g = g_xs.to(p.device, p.dtype)
@@ -469,9 +502,13 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, l
                          device=p.device)
     _lib.check(lib.map_backward(ctypes.byref(p.struct), _ptr(S), _ptr(v), _ptr(xs), _ptr(Ps),
                                 _ptr(obj), _ptr(gl), _ptr(gm), _ptr(gx), _ptr(mu), _ptr(vmu),
-                                _ptr(gxt), _ptr(ge), _ptr(ws), ws.numel(), _stream()))
+                                _ptr(gxt), _ptr(ge), _ptr(ckpt),
+                                ckpt.numel() if ckpt is not None else 0, _ptr(ws), ws.numel(),
+                                _stream()))
     r = _nat(p, dict(xs=xs, Ps=Ps, obj=obj, g_loglik=gl, g_obj=gm, mu=mu, g_xs_theta=gxt),
              natural)
+    if ckpt is not None:
+        r.update(_nat(p, dict(S=S, v=v), natural))
     if ge is not None:
         r["g_elems"] = from_tiled(ge, 2 * elem_grad_size(p), p.n_states) if natural else ge
     return r
@@ -479,8 +516,11 @@ def backward(p: Problem, S, v, covariances=True, objective=True, natural=True, l
 
 class GraphedSmooth:
     """A launch sequence of `smooth` (form "rts"), of `two_filter_smooth`
-    (form "two_filter") or of `iterated_nonlinear` from m0 with `n_iter`
-    iterations (form "iterated") captured once into a HIP graph
+    (form "two_filter"), of `iterated_nonlinear` from m0 with `n_iter`
+    iterations (form "iterated") or of the checkpointed training step (form
+    "checkpointed": `smooth(..., checkpoint=True)` for x*, the log-likelihood
+    and the objective, then `backward` from the checkpoint for P^s and the
+    gradients, into the same output keys) captured once into a HIP graph
     (torch.cuda.CUDAGraph on ROCm) with fixed output buffers, then replayed.
     Inputs are read from the Problem's device buffers at replay time, so
     refreshing their contents in place (same shapes) is seen by the next
@@ -489,10 +529,12 @@ class GraphedSmooth:
 
     def __init__(self, p: Problem, covariances=True, loglik=True, objective=True, grad=False,
                  form="rts", n_iter=1):
-        if form not in ("rts", "two_filter", "iterated"):
-            raise ValueError("form must be 'rts', 'two_filter' or 'iterated'")
+        if form not in ("rts", "two_filter", "iterated", "checkpointed"):
+            raise ValueError("form must be 'rts', 'two_filter', 'iterated' or 'checkpointed'")
         if form == "two_filter" and (objective or grad):
             raise ValueError("the two-filter form has no objective or gradients")
+        if form == "checkpointed" and not grad:
+            raise ValueError("the checkpointed form is a training step: grad=True")
         self.p = p
         f64 = torch.float64
         self.out = dict(S=p._tiled(p.nsym), v=p._tiled(p.nx), xs=p._tiled(p.nx),
@@ -503,7 +545,17 @@ class GraphedSmooth:
                         g_loglik=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None,
                         g_obj=p._empty(p.n_seg, p.n_theta, dtype=f64) if grad else None)
         kw = dict(covariances=covariances, loglik=loglik)
-        if form == "rts":
+        if form == "checkpointed":
+            self.out["ckpt"] = torch.empty(checkpoint_bytes(p), dtype=torch.uint8,
+                                           device=p.device)
+
+            def run():
+                smooth(p, out=self.out, natural=False, covariances=False, loglik=loglik,
+                       objective=objective, grad=False, checkpoint=True)
+                backward(p, self.out["S"], self.out["v"], covariances=covariances,
+                         objective=objective, natural=False, loglik_grad=grad, obj_grad=grad,
+                         ckpt=self.out["ckpt"], out=self.out)
+        elif form == "rts":
             def run():
                 smooth(p, out=self.out, natural=False, objective=objective, grad=grad, **kw)
         elif form == "two_filter":
@@ -540,22 +592,29 @@ class MapSmooth(torch.autograd.Function):
     planes S, v kept from the forward pass.  theta is [n_seg, n_theta]
     (per segment), or [n_theta] / [1, n_theta] shared by every segment (its
     gradient is then the sum over segments).  Nonlinear models are
-    linearised about the problem's xbar, held fixed."""
+    linearised about the problem's xbar, held fixed.  With `checkpoint`
+    (third argument), only the filter checkpoint is kept instead of S, v
+    (map_smooth_checkpointed), and a cotangent on xs rebuilds them from it."""
 
     @staticmethod
-    def forward(ctx, theta, problem: Problem):
+    def forward(ctx, theta, problem: Problem, checkpoint=False):
         problem.set_theta(theta.detach())
         r = smooth(problem, covariances=False, loglik=True, objective=True, grad=True,
-                   natural=False)
+                   natural=False, checkpoint=checkpoint)
         ctx.problem = problem
-        ctx.save_for_backward(r["g_loglik"], r["g_obj"], r["S"], r["v"], theta.detach().clone())
+        ctx.checkpoint = bool(checkpoint)
+        if checkpoint:
+            kept = (r["ckpt"],)
+        else:
+            kept = (r["S"], r["v"])
+        ctx.save_for_backward(r["g_loglik"], r["g_obj"], theta.detach().clone(), *kept)
         ctx.theta_shape = theta.shape
         ctx.theta_dtype = theta.dtype
         return problem.natural(r["xs"], problem.nx), r["loglik"], r["obj"]
 
     @staticmethod
     def backward(ctx, g_xs, g_ll, g_obj):
-        gl, gm, S, v, theta = ctx.saved_tensors
+        gl, gm, theta, *kept = ctx.saved_tensors
         g = torch.zeros_like(gl)
         if g_ll is not None:
             g = g + g_ll[:, None] * gl
@@ -564,10 +623,14 @@ class MapSmooth(torch.autograd.Function):
         if g_xs is not None and bool((g_xs != 0).any()):
             p = ctx.problem
             p.set_theta(theta)   # the forward pass's theta (the problem may have moved on)
-            r = backward(p, S, v, covariances=False, objective=False, natural=False,
-                         loglik_grad=False, obj_grad=False, g_xs=g_xs)
+            if ctx.checkpoint:
+                r = backward(p, None, None, covariances=False, objective=False, natural=False,
+                             loglik_grad=False, obj_grad=False, g_xs=g_xs, ckpt=kept[0])
+            else:
+                r = backward(p, kept[0], kept[1], covariances=False, objective=False,
+                             natural=False, loglik_grad=False, obj_grad=False, g_xs=g_xs)
             g = g + r["g_xs_theta"]
         if tuple(ctx.theta_shape) != tuple(g.shape):
             # one theta shared by every segment ([n_theta] or [1, n_theta])
             g = g.sum(0, keepdim=True)
-        return g.to(ctx.theta_dtype).reshape(ctx.theta_shape), None
+        return g.to(ctx.theta_dtype).reshape(ctx.theta_shape), None, None

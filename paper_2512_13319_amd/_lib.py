@@ -17,7 +17,7 @@ STATUS = {0: "MAP_OK", -1: "MAP_E_ARG", -2: "MAP_E_DIM", -3: "MAP_E_DTYPE", -4: 
 # every symbol include/mapscan.h declares
 EXPORTS = ["map_workspace_bytes", "map_workspace_init", "map_build_elements", "map_filter_scan",
            "map_smoother_scan", "map_smooth", "map_smooth_noalloc", "map_two_filter_smooth", "map_dense_output", "map_iterated_nonlinear",
-           "map_backward",
+           "map_backward", "map_checkpoint_bytes", "map_smooth_checkpointed",
            "map_autotune", "map_lti_exact_terms", "map_schedule", "map_profile_enable", "map_profile_reset", "map_profile_read",
            "map_last_error", "map_abi_version"]
 PROF_KINDS = {"filter_up": 0, "filter_down": 1, "fused_down": 2, "traj_up": 3, "traj_down": 4,
@@ -81,7 +81,11 @@ def load(path: str | None = None):
     lib.map_dense_output.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     lib.map_two_filter_smooth.argtypes = [P, vp, vp, vp, vp, dp, vp, sz, vp]
     lib.map_iterated_nonlinear.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp]
-    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, dp, vp, sz, vp]
+    lib.map_backward.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, dp, dp, vp, sz, vp, sz,
+                                 vp]
+    lib.map_checkpoint_bytes.argtypes = [P]
+    lib.map_checkpoint_bytes.restype = sz
+    lib.map_smooth_checkpointed.argtypes = [P, vp, vp, vp, vp, dp, dp, dp, dp, vp, sz, vp, sz, vp]
     lib.map_autotune.argtypes = [P, vp, sz, ctypes.c_char_p, ctypes.POINTER(i32), vp]
     lib.map_schedule.argtypes = [P, ctypes.POINTER(i32)]
     lib.map_lti_exact_terms.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]
@@ -94,7 +98,8 @@ def load(path: str | None = None):
     lib.map_abi_version.restype = ctypes.c_int32
     for name in EXPORTS:
         getattr(lib, name)
-        if name not in ("map_workspace_bytes", "map_last_error", "map_abi_version"):
+        if name not in ("map_workspace_bytes", "map_checkpoint_bytes", "map_last_error",
+                        "map_abi_version"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -576,6 +576,11 @@ struct Ws {
   // split, see later_chunk): its lane g1 holds the start of lane g >> k1_shift
   int64_t n_lanes1, n_tiles1, chunk1;
   int k1_shift;
+  // 1: the filter up-sweep's last block scans the block aggregates into
+  // tile_carry; 0: tile_carry already holds those carries (a checkpoint of an
+  // earlier forward pass on the same problem and schedule), and the up-sweep
+  // only rebuilds the lane and tile prefixes inside each block
+  int up_tail;
   unsigned int* status;    // MAP_CHECK_FINITE: set to 1 when a non-finite value is written; else null
 };
 
@@ -1512,7 +1517,8 @@ k_filter_up(Prob<TS> p, Ws<T> ws, Acc zacc) {
     unpack_elem(s_blk[2], pre);
     lds_step(s_blk[4], pre);
   }
-  const bool last = arrive_last(ws.counters + kCountersFilter);
+  // (the carries of a checkpoint need no arrival: up_tail is the same for the whole grid)
+  const bool last = ws.up_tail && arrive_last(ws.counters + kCountersFilter);
   // tile prefixes: read only by the next kernel, written after the arrival
   if (lane == 0 && wv > 0 && tile < ws.n_tiles) store_elem(ws.tile_pre, ws.n_tiles, tile, pre);
   if (last) {

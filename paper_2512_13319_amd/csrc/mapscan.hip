@@ -405,6 +405,29 @@ map_status check_ws(const map_problem& p, void* ws, size_t ws_bytes, bool allow_
   return MAP_OK;
 }
 
+// Bytes of a filter checkpoint at the flat schedule the adjoint resolves.
+size_t ckpt_need(const map_problem& p) {
+  return size_t(checkpoint_values(p.nx, p.n_steps + p.n_seg, sched::resolve(p, false))) *
+         compute_bytes(p.dtype);
+}
+
+map_status check_ckpt(const map_problem& p, const void* ckpt, size_t ckpt_bytes, const void* ws,
+                      size_t ws_bytes, const char* what) {
+  if (p.model == MAP_MODEL_LINEAR)
+    return fail(MAP_E_UNSUPPORTED, "%s: checkpoints serve map_backward, which needs a parametric "
+                                   "model", what);
+  if (p.n_sub > 1)
+    return fail(MAP_E_UNSUPPORTED, "%s: no checkpoints for sub-stepped blocks", what);
+  const size_t need = ckpt_need(p);
+  if (ckpt_bytes < need)
+    return fail(MAP_E_ARG, "%s: checkpoint has %zu bytes, needs %zu", what, ckpt_bytes, need);
+  const char* c = static_cast<const char*>(ckpt);
+  const char* w = static_cast<const char*>(ws);
+  if (w != nullptr && c < w + ws_bytes && w < c + need)
+    return fail(MAP_E_ARG, "%s: the checkpoint overlaps the workspace", what);
+  return MAP_OK;
+}
+
 struct DoBuild {
   const map_problem& p;
   void* elems;
@@ -537,6 +560,35 @@ map_status map_smooth(const map_problem* p, void* S, void* v, void* xs, void* Ps
   return finish_check(*p, ws, a.stream, dispatch(*p, DoSmooth{*p, a}));
 }
 
+size_t map_checkpoint_bytes(const map_problem* p) {
+  if (validate(p, false) != MAP_OK) return 0;
+  return ckpt_need(*p);
+}
+
+map_status map_smooth_checkpointed(const map_problem* p, void* S, void* v, void* xs, void* Ps,
+                                   double* loglik, double* obj, double* g_loglik, double* g_obj,
+                                   void* ckpt, size_t ckpt_bytes, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  map_status s = validate(p);
+  if (s != MAP_OK) return s;
+  if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
+  if (ckpt == nullptr) return fail(MAP_E_ARG, "map_smooth_checkpointed: ckpt is NULL");
+  {
+    const void* others[8] = {S, v, xs, Ps, loglik, obj, g_loglik, g_obj};
+    for (const void* o : others)
+      if (o == ckpt) return fail(MAP_E_ARG, "map_smooth_checkpointed: ckpt aliases an output");
+  }
+  if ((s = check_ckpt(*p, ckpt, ckpt_bytes, ws, ws_bytes, "map_smooth_checkpointed")) != MAP_OK)
+    return s;
+  if ((s = check_divergence(*p, loglik || g_loglik || g_obj, "map_smooth_checkpointed")) != MAP_OK)
+    return s;
+  if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
+  SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, loglik, obj, g_loglik, g_obj, ws,
+               static_cast<hipStream_t>(stream), sched::resolve(*p, false)};
+  a.ckpt = ckpt;
+  return finish_check(*p, ws, a.stream, dispatch(*p, DoSmooth{*p, a}));
+}
+
 map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, void* Ps,
                               double* loglik, double* obj, double* g_loglik, double* g_obj,
                               void* stream) {
@@ -643,19 +695,33 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
   return finish_check(*p, ws, st, MAP_OK);
 }
 
-map_status map_backward(const map_problem* p, const void* S, const void* v, void* xs, void* Ps,
+map_status map_backward(const map_problem* p, void* S, void* v, void* xs, void* Ps,
                         double* obj, double* g_loglik, double* g_obj, const void* g_xs, void* mu,
-                        void* vmu, double* g_xs_theta, double* g_elems, void* ws, size_t ws_bytes,
-                        void* stream) {
+                        void* vmu, double* g_xs_theta, double* g_elems, const void* ckpt,
+                        size_t ckpt_bytes, void* ws, size_t ws_bytes, void* stream) {
   map_status s = validate(p);
   if (s != MAP_OK) return s;
   if (S == nullptr || v == nullptr || xs == nullptr) return fail(MAP_E_ARG, "S/v/xs is NULL");
   if (g_loglik == nullptr && g_obj == nullptr && g_xs == nullptr && g_elems == nullptr)
     return fail(MAP_E_ARG, "nothing to differentiate: g_loglik, g_obj, g_xs and g_elems are NULL");
   if (g_elems != nullptr) {
-    const void* others[9] = {S, v, xs, Ps, obj, g_loglik, g_obj, g_xs, g_xs_theta};
+    const void* others[10] = {S, v, xs, Ps, obj, g_loglik, g_obj, g_xs, g_xs_theta, ckpt};
     for (const void* o : others)
       if (o == g_elems) return fail(MAP_E_ARG, "g_elems aliases another buffer");
+  }
+  if (ckpt != nullptr) {
+    // S, v are rebuilt (written) here: distinct from each other, from the
+    // other outputs and from the checkpoint
+    const void* outs[7] = {S, v, xs, Ps, obj, g_loglik, g_obj};
+    for (int a = 0; a < 2; ++a)
+      for (int b = a + 1; b < 7; ++b)
+        if (outs[a] == outs[b])
+          return fail(MAP_E_ARG, "map_backward: with a checkpoint, S and v are outputs and must "
+                                 "not alias each other or another output");
+    const void* others[11] = {S, v, xs, Ps, obj, g_loglik, g_obj, g_xs, mu, vmu, g_xs_theta};
+    for (const void* o : others)
+      if (o == ckpt) return fail(MAP_E_ARG, "map_backward: the checkpoint aliases another buffer");
+    if ((s = check_ckpt(*p, ckpt, ckpt_bytes, ws, ws_bytes, "map_backward")) != MAP_OK) return s;
   }
   if (g_xs != nullptr) {
     if (mu == nullptr || vmu == nullptr || g_xs_theta == nullptr)
@@ -672,8 +738,9 @@ map_status map_backward(const map_problem* p, const void* S, const void* v, void
   if ((s = check_blocks(*p, true, "map_backward")) != MAP_OK) return s;
   if ((s = check_ws(*p, ws, ws_bytes, false)) != MAP_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SmoothArgs a{const_cast<void*>(S), const_cast<void*>(v), nullptr, nullptr, xs, Ps, nullptr, obj,
+  SmoothArgs a{S, v, nullptr, nullptr, xs, Ps, nullptr, obj,
                g_loglik, g_obj, ws, st, sched::resolve(*p, false), g_elems};
+  a.ckpt = const_cast<void*>(ckpt);
   s = dispatch(*p, DoSmoother{*p, a, g_loglik != nullptr || g_obj != nullptr || g_elems != nullptr});
   if (s == MAP_OK && g_xs != nullptr)
     s = dispatch(*p, DoIft{*p, a, IftArgs{g_xs, mu, vmu, g_xs_theta}});

@@ -88,6 +88,13 @@ inline WsLayout ws_layout(int nx, int64_t n_states, size_t sz, int64_t chunk) {
   return w;
 }
 
+// Values in a filter checkpoint: (S, v) before every block of four tiles of
+// the filter up-sweep's decomposition (the carries its last block scans).
+inline int64_t checkpoint_values(int nx, int64_t n_states, int chunk) {
+  const int64_t sym = nx * (nx + 1) / 2;
+  return (sym + nx) * ((work_tiles(n_states, chunk) + 3) / 4);
+}
+
 struct SmoothArgs {
   void* S;
   void* v;
@@ -103,6 +110,9 @@ struct SmoothArgs {
   hipStream_t stream;
   int chunk;  // states per lane (4, 8, 16 or 32)
   double* g_elems = nullptr;  // map_backward: per-step element cotangents (flat schedules)
+  // filter checkpoint (checkpoint_values of the arithmetic type): written by
+  // the fused step, read by the adjoint, which then rebuilds S, v into a.S, a.v
+  void* ckpt = nullptr;
 };
 
 // Implicit-function VJP (map_backward with a cotangent of x*).

@@ -68,6 +68,7 @@ inline Ws<T> make_ws(int nx, int64_t n_states, void* base, int chunk, int flags)
   w.n_tiles1 = l.n_tiles1;
   w.chunk1 = chunk;
   w.k1_shift = chunk == 32 ? 1 : 0;
+  w.up_tail = 1;
   w.status = (flags & MAP_CHECK_FINITE) ? w.counters + kStatusWord : nullptr;
   return w;
 }
@@ -216,14 +217,30 @@ hipError_t Runner<TS, T, M>::smoother(const map_problem& q, const SmoothArgs& a,
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
   const int64_t nth = M::NTH;
-  MS_CHECK(zero(Acc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr},
-                q.n_seg, nth, a.stream));
   const unsigned g = grid_for(w.n_tiles);
   FilterOut fo{a.S, a.v, nullptr, nullptr, 0};
   Acc acc{nullptr, a.obj, a.g_loglik, a.g_obj};
-  prof_begin(kProfTrajUp, a.stream);
-  k_filter_down<TS, T, M, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
-  prof_end(kProfTrajUp, a.stream);
+  const Acc zacc{nullptr, a.obj, grad ? a.g_loglik : nullptr, grad ? a.g_obj : nullptr};
+  if (a.ckpt != nullptr) {
+    // From a filter checkpoint: the up-sweep rebuilds the lane and tile
+    // prefixes inside each block (and zeroes the accumulators), the block
+    // carries are the checkpoint's, and the fused fix-up writes S, v again
+    // while it builds the trajectory maps.
+    w.tile_carry = static_cast<T*>(a.ckpt);
+    w.up_tail = 0;
+    prof_begin(kProfFilterUp, a.stream);
+    launch_filter_up<TS, T, M>(grid_for(w.n_tiles1), a.stream, p, up_view(w), zacc);
+    prof_end(kProfFilterUp, a.stream);
+    MS_CHECK(hipGetLastError());
+    prof_begin(kProfFused, a.stream);
+    k_filter_down<TS, T, M, kModeFused><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+    prof_end(kProfFused, a.stream);
+  } else {
+    MS_CHECK(zero(zacc, q.n_seg, nth, a.stream));
+    prof_begin(kProfTrajUp, a.stream);
+    k_filter_down<TS, T, M, kModeTrajOnly><<<g, kBlock, 0, a.stream>>>(p, w, fo, acc);
+    prof_end(kProfTrajUp, a.stream);
+  }
   MS_CHECK(hipGetLastError());
   TrajOut to{a.S, a.v, a.xs, a.Ps, a.obj != nullptr, grad, grad ? a.g_elems : nullptr};
   return launch_traj_down<TS, T, M>(p, w, to, acc, grad, g, a.stream);
@@ -294,6 +311,8 @@ hipError_t Runner<TS, T, M>::smooth(const map_problem& q, const SmoothArgs& a) {
   }
   Prob<TS> p = make_prob<TS>(q);
   Ws<T> w = make_ws<T>(M::NX, p.n_states, a.ws, a.chunk, q.flags);
+  // checkpointed: the up-sweep's block carries go straight to the checkpoint
+  if (a.ckpt != nullptr) w.tile_carry = static_cast<T*>(a.ckpt);
   const bool grad = a.g_loglik != nullptr || a.g_obj != nullptr;
   const unsigned g = grid_for(w.n_tiles);
   prof_begin(kProfFilterUp, a.stream);

@@ -119,7 +119,7 @@ def test_flags_are_validated(seg):
     assert lib.map_two_filter_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE,
                                      1 << 40, None) == -8
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, None, None,
-                            None, None, None, None, FAKE, 1 << 40, None) == -8
+                            None, None, None, None, None, 0, FAKE, 1 << 40, None) == -8
     assert b"MAP_OM_DIVERGENCE" in lib.map_last_error()
     assert "#define MAP_OM_DIVERGENCE %d" % _lib.MAP_OM_DIVERGENCE in open(HEADER).read()
     p.flags = 4
@@ -198,17 +198,17 @@ def test_workspace_and_output_checks(seg):
                                  None) == -1
     # nothing to differentiate
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, None, None,
-                            None, None, None, FAKE, 1 << 40, None) == -1
+                            None, None, None, None, 0, FAKE, 1 << 40, None) == -1
     # a cotangent of x* needs mu, vmu and the output, none of them aliasing the inputs
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, None, FAKE, None,
-                            FAKE + 64, FAKE + 128, None, FAKE, 1 << 40, None) == -1
+                            FAKE + 64, FAKE + 128, None, None, 0, FAKE, 1 << 40, None) == -1
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE + 8, FAKE + 16, None, None, None, None,
-                            FAKE + 24, FAKE + 16, FAKE + 32, FAKE + 40, None, FAKE, 1 << 40,
-                            None) == -1
+                            FAKE + 24, FAKE + 16, FAKE + 32, FAKE + 40, None, None, 0, FAKE,
+                            1 << 40, None) == -1
     assert b"distinct" in lib.map_last_error()
     # per-step element cotangents must not alias another buffer
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE + 8, FAKE + 16, None, None, None, None,
-                            None, None, None, None, FAKE + 16, FAKE, 1 << 40, None) == -1
+                            None, None, None, None, FAKE + 16, None, 0, FAKE, 1 << 40, None) == -1
     assert b"g_elems aliases" in lib.map_last_error()
     assert lib.map_iterated_nonlinear(ctypes.byref(p), 0, None, FAKE, FAKE, FAKE, FAKE, None, None,
                                       None, None, None, FAKE, 1 << 40, None) == -1
@@ -216,6 +216,75 @@ def test_workspace_and_output_checks(seg):
                                       None, None, None, FAKE, 1 << 40, None) == -1  # aliasing
     assert lib.map_build_elements(ctypes.byref(p), None, None) == -1
     assert lib.map_filter_scan(None, FAKE, FAKE, None, None, None, FAKE, 1 << 40, None) == -1
+
+
+def work_tiles(n_states, chunk):
+    ts = 64 * chunk
+    full, rem = divmod(n_states, ts)
+    return full if (full > 0 and 0 < rem <= 8) else -(-n_states // ts)
+
+
+def test_checkpoint_size_and_arguments():
+    """The filter checkpoint holds (S, v) -- nx(nx+1)/2 + nx values of the
+    arithmetic type -- per block of four work tiles of the schedule the
+    adjoint resolves; the checkpointed entry points reject a missing, short,
+    aliased or workspace-overlapping checkpoint, and problems the adjoint
+    does not take, before launching anything."""
+    lib = _lib.load()
+    big = np.array([0, 5000, 12000, 40000], dtype=np.int64)   # 40003 states
+    ns = 40003
+    for chunk in (4, 8, 16, 32):
+        for dtype, size in ((_lib.MAP_F64, 8), (_lib.MAP_F32, 8), (_lib.MAP_F32_FAST, 4)):
+            p = good(big)
+            p.chunk, p.dtype = chunk, dtype
+            blocks = -(-work_tiles(ns, chunk) // 4)
+            assert lib.map_checkpoint_bytes(ctypes.byref(p)) == 14 * blocks * size
+    p = good(big)
+    p.chunk = 16
+    need = lib.map_checkpoint_bytes(ctypes.byref(p))
+    assert need == 14 * 10 * 8          # 40 work tiles of 1024 states, 10 blocks
+    bad = good(big)
+    bad.nx = 9
+    assert lib.map_checkpoint_bytes(ctypes.byref(bad)) == 0
+    WS, CK = FAKE, FAKE + (1 << 41)      # a workspace of 2^40 bytes, the checkpoint past it
+
+    def fwd(prob, ck, ck_bytes, S=FAKE + 8, ws_bytes=1 << 40):
+        return lib.map_smooth_checkpointed(ctypes.byref(prob), S, FAKE + 16, FAKE + 24, None,
+                                           None, None, FAKE + 32, None, ck, ck_bytes, WS,
+                                           ws_bytes, None)
+
+    assert fwd(p, None, need) == -1
+    assert b"ckpt is NULL" in lib.map_last_error()
+    assert fwd(p, CK, need - 1) == -1
+    assert b"checkpoint has" in lib.map_last_error()
+    assert fwd(p, CK, need, S=CK) == -1
+    assert b"aliases" in lib.map_last_error()
+    assert fwd(p, WS + 4096, need) == -1
+    assert b"overlaps the workspace" in lib.map_last_error()
+    assert fwd(p, CK, need, ws_bytes=16) == -7        # workspace too small: still checked
+    lin = good(big)
+    lin.model = _lib.MODELS["linear"]
+    lin.n_theta = 0
+    for k in ("F", "c", "L", "W", "H", "r", "R"):
+        setattr(lin, k, FAKE)
+    assert fwd(lin, CK, 1 << 30) == -8
+    blk = good(big)
+    blk.n_sub = 4
+    assert fwd(blk, CK, 1 << 30) == -8
+
+    def bwd(ck, ck_bytes, S=FAKE + 8, v=FAKE + 16, xs=FAKE + 24, g_obj=FAKE + 40):
+        return lib.map_backward(ctypes.byref(p), S, v, xs, None, None, FAKE + 32, g_obj, None,
+                                None, None, None, None, ck, ck_bytes, WS, 1 << 40, None)
+
+    assert bwd(CK, need - 8) == -1
+    assert b"checkpoint has" in lib.map_last_error()
+    assert bwd(CK, need, v=FAKE + 8) == -1               # S and v are outputs: distinct
+    assert b"S and v are outputs" in lib.map_last_error()
+    assert bwd(CK, need, xs=FAKE + 16) == -1
+    assert bwd(CK, need, g_obj=CK) == -1
+    assert b"checkpoint aliases" in lib.map_last_error()
+    assert bwd(WS + 256, need) == -1
+    assert b"overlaps the workspace" in lib.map_last_error()
 
 
 def test_gradients_need_parametric_model():
@@ -230,7 +299,7 @@ def test_gradients_need_parametric_model():
     assert lib.map_smooth(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, FAKE, FAKE, FAKE,
                           1 << 40, None) == -8
     assert lib.map_backward(ctypes.byref(p), FAKE, FAKE, FAKE, None, None, FAKE, FAKE, None, None,
-                            None, None, None, FAKE, 1 << 40, None) == -8
+                            None, None, None, None, 0, FAKE, 1 << 40, None) == -8
     p.R = None
     assert lib.map_filter_scan(ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, 1 << 40,
                                None) == -1
