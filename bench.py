@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--no-checkpointed", action="store_true",
                     help="skip the checkpointed training step (filter checkpoint, adjoint "
                          "rebuilds S, v)")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32-storage run of the headline step")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the exact-discretisation (linear-model path) measurement")
     ap.add_argument("--ct-chunk", type=int, default=0,
@@ -291,6 +293,36 @@ def main():
                       "roofline": roofline_for(kern_tf, rec, fresh, p.n_states, p.nx, p.ny, s,
                                                args.dtype, chunk)}
 
+    fp32 = None
+    if args.dtype == "f64" and not args.no_fp32:
+        # the headline step with FP32 storage of inputs and outputs (FP64
+        # arithmetic and workspace), on the same track rounded to FP32
+        p32 = ms.problem_from_workload(wl, dtype=torch.float32, device=dev)
+        if tuned:
+            ms.autotune(p32)
+        out32 = dict(S=p32._tiled(nsym), v=p32._tiled(p32.nx), xs=p32._tiled(p32.nx),
+                     Ps=p32._tiled(nsym), loglik=p32._empty(1, dtype=torch.float64),
+                     obj=p32._empty(1, dtype=torch.float64),
+                     g_loglik=p32._empty(1, 3, dtype=torch.float64),
+                     g_obj=p32._empty(1, 3, dtype=torch.float64))
+
+        def step_fa32():
+            ms.smooth(p32, covariances=True, loglik=True, objective=True, grad=True, out=out32,
+                      natural=False)
+
+        ms_32_e, _, kern_32 = timed(step_fa32, args.steps, args.warmup, True)
+        if args.no_graph:
+            ms_32 = ms_32_e
+        else:
+            g_32 = ms.GraphedSmooth(p32, covariances=True, loglik=True, objective=True,
+                                    grad=True)
+            ms_32, _, _ = timed(g_32.replay, args.steps, args.warmup, False)
+        fp32 = {"value": T / (ms_32 * 1e-3), "unit": "time-steps/s", "ms_per_step": ms_32,
+                "eager_ms_per_step": round(ms_32_e, 4), "storage": "f32",
+                "arithmetic": "f64",
+                "schedule": schedule_info(ms.schedule(p32), tuned),
+                "kernels_ms": {k: round(v[1], 4) for k, v in kern_32.items()}}
+
     checkpointed = None
     if not args.no_checkpointed:
         # the same training step with activation checkpointing: the forward
@@ -352,6 +384,8 @@ def main():
     }
     if two_filter is not None:
         res["two_filter"] = two_filter
+    if fp32 is not None:
+        res["fp32_storage"] = fp32
     if checkpointed is not None:
         res["checkpointed"] = checkpointed
 
