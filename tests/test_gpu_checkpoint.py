@@ -193,3 +193,34 @@ def test_checkpointed_adjoint_full_size(cfg, dtype):
         e = _sum_err(b[k], r[k])
         print(f"  {k}: {e:.1e}")
         assert e <= SUM_TOL, k
+
+
+@pytest.mark.parametrize("case", ["empty_segments", "no_steps", "f32_arithmetic"])
+def test_checkpointed_edge_cases(case):
+    """Empty segments between others, a problem without steps (every
+    segment its prior, one block), and FP32 arithmetic (an FP32 checkpoint):
+    the rebuilt planes, x* and P^s equal the forward call's bit for bit."""
+    import paper_2512_13319_amd as ms
+    arith, dtype, chunk = "f64", "f64", 4
+    if case == "empty_segments":
+        wl = workloads.cv_batched(lens=[0, 1500, 0, 0, 533, 0, 1, 0], seed=18)
+    elif case == "no_steps":
+        wl = workloads.cv_batched(lens=[0, 0, 0, 0, 0], seed=20)
+    else:
+        wl, arith, dtype, chunk = _ragged("f32"), "f32", "f32", 16
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype], chunk=chunk, arith=arith)
+    print(f"{case}: {wl.n_states} states", flush=True)
+    r = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True, natural=False,
+                  checkpoint=True)
+    b = ms.backward(p, None, None, covariances=True, objective=True, natural=False,
+                    ckpt=r["ckpt"])
+    torch.cuda.synchronize()
+    # 14 values of the arithmetic type per block
+    assert r["ckpt"].numel() == ms.checkpoint_bytes(p)
+    assert r["ckpt"].numel() % (14 * (4 if arith == "f32" else 8)) == 0
+    for k in ("S", "v", "xs", "Ps"):
+        assert _same_states(p, b[k], r[k], k), k
+    for k in ("obj", "g_loglik", "g_obj"):
+        e = _sum_err(b[k], r[k])
+        print(f"  {k}: {e:.1e}")
+        assert e <= SUM_TOL, k
