@@ -59,3 +59,33 @@ def test_random_batches(seed, dtype):
     msg = f"seed {seed} {dtype}: xs {e_xs:.1e} Ps {e_Ps:.1e} ll {e_ll:.1e} obj {e_ob:.1e}"
     print(msg)
     assert max(e_xs, e_Ps, e_ll, e_ob) <= tol, msg
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("seed", [s for s in range(12) if s % 3 != 2])
+def test_random_batches_checkpointed(seed, dtype):
+    """The same random constant-velocity batches through the checkpoint mode
+    (map_smooth_checkpointed, then map_backward from the checkpoint, on the
+    flat schedule the adjoint resolves): x* against the oracle at the sweep's
+    bar, and the rebuilt S, v, x*, P^s equal the forward call's bit for bit."""
+    import paper_2512_13319_amd as ms
+    wl, chunk = _case(seed)
+    wl = wl.rounded(dtype)
+    print(f"checkpointed sweep seed {seed} {dtype}: {wl.n_seg} segments, {wl.n_steps} steps, "
+          f"chunk {chunk}", flush=True)
+    o = cref.smooth(wl)
+    p = ms.problem_from_workload(wl, dtype=TORCH_DT[dtype], chunk=chunk)
+    f = ms.smooth(p, covariances=True, loglik=True, objective=True, grad=True, natural=False,
+                  checkpoint=True)
+    b = ms.backward(p, None, None, covariances=True, objective=True, natural=False,
+                    ckpt=f["ckpt"])
+    torch.cuda.synchronize()
+    comps = dict(S=p.nsym, v=p.nx, xs=p.nx, Ps=p.nsym)
+    for k, c in comps.items():
+        assert torch.equal(p.natural(b[k], c), p.natural(f[k], c)), k
+    for k in ("obj", "g_loglik", "g_obj"):
+        a, r = b[k].cpu().numpy(), f[k].cpu().numpy()
+        assert np.abs(a - r).max() <= 1e-12 * max(np.abs(r).max(), 1e-300), k
+    e_xs = rel_err(planes_T(p.natural(b["xs"], p.nx)), o["xs"])
+    print(f"  xs vs oracle {e_xs:.1e}")
+    assert e_xs <= TOL[dtype]
