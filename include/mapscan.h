@@ -267,7 +267,7 @@ map_status map_smooth_noalloc(const map_problem* p, void* S, void* v, void* xs, 
  * prefixes and then S, v at every state are rebuilt locally, with no
  * cross-block step.  Between a forward call and its adjoint the caller then
  * keeps (nx(nx+1)/2 + nx) values per block instead of per state (at chunk 16,
- * one per 4096 states; 3.6 KB at nx = 4 and 2^20 steps, against 117 MB of
+ * one per 4096 states: 28 KB at nx = 4 and 2^20 steps, against 117 MB of
  * S, v planes).
  *
  * map_checkpoint_bytes: bytes of that checkpoint for this problem (0 if the

@@ -243,6 +243,16 @@ def test_checkpoint_size_and_arguments():
     p.chunk = 16
     need = lib.map_checkpoint_bytes(ctypes.byref(p))
     assert need == 14 * 10 * 8          # 40 work tiles of 1024 states, 10 blocks
+    # the sizes the documentation quotes: 2^20 steps at 16 per lane (1024 work
+    # tiles, the one-state tail merged), and the 4096-segment batch at 32
+    one = good(np.array([0, 2 ** 20], dtype=np.int64))
+    one.chunk = 16
+    assert lib.map_checkpoint_bytes(ctypes.byref(one)) == 28672
+    batch = good(np.array([0, 16224882 - 4095], dtype=np.int64))   # 16228978 states
+    batch.n_seg, batch.n_steps = 4096, 16224882
+    batch.seg_off_host = None
+    batch.chunk, batch.dtype = 32, _lib.MAP_F32
+    assert lib.map_checkpoint_bytes(ctypes.byref(batch)) == 1982 * 14 * 8
     bad = good(big)
     bad.nx = 9
     assert lib.map_checkpoint_bytes(ctypes.byref(bad)) == 0
