@@ -347,8 +347,10 @@ map_status map_iterated_nonlinear(const map_problem* p, int32_t n_iter, const vo
  * rebuilt from the checkpoint's block carries (one more filter up-sweep
  * without its cross-block step, and the filter fix-up fused with the
  * trajectory maps) and written there, distinct from each other and from every
- * other buffer; the results equal those of the call with the saved planes.
- * Reverse-scans the same elements to rebuild xs and
+ * other buffer.  The rebuilt planes equal the forward call's, and x*, P^s and
+ * the gradients equal map_smooth's on the same schedule (the call with saved
+ * planes agrees with them to rounding: with FP32 storage its trajectory maps
+ * start from the rounded planes).  Reverse-scans the same elements to rebuild xs and
  * Ps (written to the caller's buffers) and accumulates, per segment
  * ([n_seg][n_theta] double, each optional):
  *   g_loglik, g_obj  d loglik / d theta (Fisher identity) and d obj / d theta
